@@ -1,0 +1,178 @@
+"""Benchmark: time-to-solution of the shell multigrid solve on one MI355X.
+
+One step = one whole solve of H u = b from u = 0 to relative residual 1e-8
+(FP32 V(2,2) cycles inside the FP64 refinement loop) on the 1024x768x70 shell
+(55M unknowns), with b and alpha already resident in HBM. The plain FP64
+multigrid solve of the same system is timed beside it, and every kernel
+launch of the timed region is bracketed by HIP events on the solver's stream
+to give the dominant kernel's achieved bandwidth against the HBM roofline.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
+                    [--no-cpu-baseline] [--no-fp64]
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 solve (s) + HBM GB/s, FP32+refine vs FP64 MG, 1024x768x70"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_roofline(stats_list, cls):
+    """Achieved algorithmic GB/s of one kernel class over the timed solves."""
+    ms = sum(s.kernels[cls]["fine_ms"] for s in stats_list)
+    nb = sum(s.kernels[cls]["fine_bytes"] for s in stats_list)
+    launches = sum(s.kernels[cls]["fine_launches"] for s in stats_list)
+    if launches == 0 or ms <= 0:
+        return None
+    avg_ms = ms / launches
+    bytes_per_launch = nb / launches
+    gbps = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"kernel": cls, "launches": launches, "avg_ms": avg_ms,
+            "bytes_per_launch": bytes_per_launch, "GBps": gbps}
+
+
+def cpu_baseline(shell, iters_gpu):
+    """The oracle, untuned, on the host: one outer iteration (one V-cycle and
+    one FP64 residual) of the same workload, scaled by the GPU's iteration
+    count to a time-to-solution."""
+    import numpy as np
+    import shellgen
+    import oracle
+    a, b = shellgen.alpha(shell), shellgen.rhs(shell)
+    t0 = time.perf_counter()
+    L = oracle.build_hierarchy(shell, a)
+    oracle.column_solve(L[0], np.zeros(shell.shape))   # pivots cached
+    t_setup = time.perf_counter() - t0
+    opt = oracle.Options(nu_pre=shell.nu_pre, nu_post=shell.nu_post)
+    t0 = time.perf_counter()
+    r = b - oracle.apply(L[0], np.zeros(shell.shape))
+    u = oracle.vcycle(L, r, opt)
+    r = b - oracle.apply(L[0], u)
+    t_iter = time.perf_counter() - t0
+    rho = float(np.linalg.norm(r) / np.linalg.norm(b))
+    log(f"cpu oracle: setup {t_setup:.1f}s, one iteration {t_iter:.1f}s (rho {rho:.3f})")
+    return {"value": t_iter * iters_gpu, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"one outer iteration (V({shell.nu_pre},{shell.nu_post}) + FP64 "
+                       f"residual) of the numpy FP64 oracle on {shell.name}: "
+                       f"{t_iter:.2f} s, scaled by the GPU's {iters_gpu} iterations; "
+                       f"setup {t_setup:.1f} s not included"),
+            "per_iteration_s": t_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="shell1024x768x70")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import shellgen
+    from paper_2307_04528_amd import Solver
+
+    sh = shellgen.workload(args.workload)
+    dev = torch.device("cuda:0")
+    log(f"workload {sh.name}: {sh.nlon}x{sh.nlat}x{sh.nlev} = {sh.n} unknowns")
+    alpha = torch.from_numpy(shellgen.alpha(sh)).to(dev)
+    b = torch.from_numpy(shellgen.rhs(sh)).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
+                          precision="mixed", profile=True)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    log(f"setup {t_setup * 1e3:.1f} ms")
+    u = torch.empty_like(b)
+
+    def run(solver, steps, warmup, label):
+        for _ in range(warmup):
+            solver.solve(b, tol=args.tol, out=u)
+        torch.cuda.synchronize()
+        times, stats = [], []
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            _, st = solver.solve(b, tol=args.tol, out=u)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            stats.append(st)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        log(f"{label}: {steps} solves in {total:.3f}s, median {statistics.median(times)*1e3:.2f} ms, "
+            f"iters {stats[-1].iters}, relres {stats[-1].relres:.2e}")
+        return times, stats, total
+
+    times, stats, total = run(S, args.steps, args.warmup, "mixed")
+    u_mixed = u.clone()
+    mean_s = total / args.steps
+    st = stats[-1]
+
+    out = {
+        "metric": METRIC, "value": mean_s, "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mean_s * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": sh.name, "grid": [sh.nlon, sh.nlat, sh.nlev],
+                   "unknowns": sh.n, "cycle": f"V({sh.nu_pre},{sh.nu_post})",
+                   "tol": args.tol, "levels": st.levels, "iters": st.iters,
+                   "precision": "FP32 V-cycle inside FP64 refinement"},
+        "median_s": statistics.median(times),
+        "relres": st.relres,
+        "setup_s": t_setup,
+        "alg_GBps": st.alg_bytes / statistics.median(times) / 1e9,
+    }
+    kern = {c: kernel_roofline(stats, c) for c in st.kernels}
+    kern = {c: v for c, v in kern.items() if v}
+    dom = max(kern, key=lambda c: kern[c]["avg_ms"] * kern[c]["launches"])
+    k = kern[dom]
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"],
+                       "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                       "avg_launch_ms": k["avg_ms"], "bytes_per_launch": k["bytes_per_launch"],
+                       "launches": k["launches"]}
+    out["fine_level_kernels"] = {c: {"GBps": v["GBps"], "avg_ms": v["avg_ms"],
+                                     "launches": v["launches"]} for c, v in kern.items()}
+
+    if not args.no_fp64:
+        S64 = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
+                                precision="fp64", profile=True)
+        times64, stats64, total64 = run(S64, args.steps, args.warmup, "fp64")
+        d = (u - u_mixed).norm() / u.norm()
+        out["fp64_solve_s"] = total64 / args.steps
+        out["fp64_iters"] = stats64[-1].iters
+        out["speedup_vs_fp64"] = (total64 / args.steps) / mean_s
+        out["mixed_vs_fp64_rel_diff"] = float(d)
+        S64.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sh, st.iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,44 @@
+"""Differentiable shell solve: u = H(alpha)^{-1} rhs as a torch.autograd.Function.
+
+Backward (implicit function theorem): with L a scalar loss and w = dL/du,
+    lambda = H^{-T} w            (adjoint solve, transposed V-cycle)
+    dL/drhs = lambda,   dL/dalpha = -lambda * V * u
+since dH/dalpha at a cell is the cell volume V on that cell's diagonal.
+Both the solve and the adjoint run in the HIP library (mg_solve,
+mg_solve_adjoint, mg_grad_alpha).
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import Solver
+
+
+class MGSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rhs: torch.Tensor, alpha: torch.Tensor, solver: Solver,
+                tol: float = 1e-8):
+        if alpha is not solver.alpha:
+            solver.update_alpha(alpha.detach().contiguous())
+        u, _ = solver.solve(rhs.detach().contiguous(), tol)
+        ctx.solver = solver
+        ctx.tol = tol
+        ctx.alpha = alpha
+        ctx.save_for_backward(u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u: torch.Tensor):
+        (u,) = ctx.saved_tensors
+        solver: Solver = ctx.solver
+        if ctx.alpha is not solver.alpha:
+            solver.update_alpha(ctx.alpha.detach().contiguous())
+        lam, _ = solver.solve_adjoint(grad_u.contiguous(), ctx.tol)
+        g_alpha = solver.grad_alpha(lam, u) if ctx.needs_input_grad[1] else None
+        g_rhs = lam if ctx.needs_input_grad[0] else None
+        return g_rhs, g_alpha, None, None
+
+
+def mg_solve(rhs: torch.Tensor, alpha: torch.Tensor, solver: Solver, tol: float = 1e-8):
+    """u = H(alpha)^{-1} rhs, differentiable in rhs and alpha."""
+    return MGSolve.apply(rhs, alpha, solver, tol)

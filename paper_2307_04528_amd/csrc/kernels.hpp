@@ -1,0 +1,114 @@
+// Device-side views and kernel launchers of the shell multigrid (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mgk {
+
+// Geometry and operator data of one level, in the precision T of the kernels
+// that read it. Fields are [k][J][i] with i fastest; plane = nI*nJ.
+template <typename T>
+struct LevelView {
+    int nI, nJ, nz;
+    long long plane;
+    const T* Tlam;   // [nz][nJ]
+    const T* Tth;    // [nz][nJ+1], face F south of row F
+    const T* Tr;     // [nz+1][nJ], face F below layer F
+    const T* M;      // [nz][plane] mass sum(alpha V)
+    const T* invp;   // [nz][plane] inverse Thomas pivots of H_z
+};
+
+// Maps between a fine level and the next coarser one.
+template <typename T>
+struct TransferView {
+    int nIc, nJc;
+    const int* crow_of;      // [nJf]   coarse row of each fine row
+    const int* prow;         // [2nJf]  latitude rows used by P
+    const T* pw;             // [2nJf]  their weights
+    const int* child_first;  // [nJc]   first fine row of each coarse row
+    const int* child_count;  // [nJc]   1 or 2
+    const int* ptrow;        // [4nJc]  fine rows gathered by P^T (-1 unused)
+    const T* ptw;            // [4nJc]
+};
+
+constexpr int kBlock = 256;
+
+inline int blocks_for(long long n) { return int((n + kBlock - 1) / kBlock); }
+
+// --- launchers (all asynchronous on `s`) ---------------------------------
+
+// y = H x, or y = f - H x when f != nullptr (difference form).
+template <typename T>
+void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s);
+
+// One damped block-Jacobi sweep (Eq. 1):
+//   xout = (1-omega) xin + omega H_z^{-1}(f + sum_h T_h xin_nb),
+// or the sweep from zero xout = omega H_z^{-1} f when xin == nullptr.
+template <typename T>
+void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
+            hipStream_t s);
+
+// fc = R (f - H x) (sum over children), or R f when x == nullptr.
+template <typename T>
+void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T* f,
+                       const T* x, T* fc, hipStream_t s);
+
+// x += P xc (bilinear, cell-centred).
+template <typename T>
+void prolong_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T* x,
+                 hipStream_t s);
+
+// xc = P^T x.
+template <typename T>
+void prolong_transpose(const LevelView<T>& F, const TransferView<T>& X, const T* x,
+                       T* xc, hipStream_t s);
+
+// Adjoint of the residual restriction: y = R^T fcb (injection);
+// fb += y; xb -= H y.
+template <typename T>
+void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X,
+                             const T* fcb, T* xb, T* fb, hipStream_t s);
+
+// One kernel of the transposed smoother chain:
+//   xb' = zin ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout if set)
+//   z   = H_z^{-1} xb';  fb = (accumulate ? fb : 0) + omega z;  zout = z if set.
+template <typename T>
+void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout,
+                      T* zout, T* fb, T omega, bool accumulate, hipStream_t s);
+
+// xb = (1-omega) xb + omega sum_h T_h z_nb (in place on xb).
+template <typename T>
+void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s);
+
+// FP64 refinement step on the finest level:
+//   unew = uin + e (or uin when e == nullptr), written to uout if set;
+//   r = b - H unew, stored as TR; per-block partial sums of r^2 in FP64.
+// Returns the number of blocks (partials written).
+template <typename TE, typename TR>
+int residual_update(const LevelView<double>& L, const double* b, const double* uin,
+                    const TE* e, double* uout, TR* r, double* partials, hipStream_t s);
+
+// Per-block partial sums of x^2.
+int norm2_partials(const double* x, long long n, double* partials, hipStream_t s);
+// out[0] = sum of partials[0..n) in a fixed order.
+void sum_partials(const double* partials, int n, double* out, hipStream_t s);
+
+// Setup: M = alpha * V (fine level) and per-block counts of alpha values that
+// are not finite and > 0 (as FP64 partials).
+int fine_mass(const LevelView<double>& L, const double* V, const double* alpha,
+              double* M, double* partials, hipStream_t s);
+// Setup: row-sum Thomas pivots of H_z; inverse pivots in FP64 and FP32 and
+// an FP32 copy of M.
+void pivots(const LevelView<double>& L, double* invp64, float* invp32, float* M32,
+            hipStream_t s);
+
+void grad_alpha(const LevelView<double>& L, const double* V, const double* lam,
+                const double* u, double* g, hipStream_t s);
+void cell_volumes(const LevelView<double>& L, const double* V, double* out, hipStream_t s);
+template <typename TA, typename TB>
+void cast(const TA* in, TB* out, long long n, hipStream_t s);
+template <typename T>
+void fill(T* out, T v, long long n, hipStream_t s);
+
+}  // namespace mgk

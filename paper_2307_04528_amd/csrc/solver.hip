@@ -1,0 +1,874 @@
+// Solver driver and C ABI (include/mg.h).
+//
+// Outer loop (paper Section 2: each iteration reduces ||b - Hu||): in FP64,
+//   r = b - H u;  while ||r|| > tol ||b||:  e = V(r);  u += e;  r = b - H u
+// with the V-cycle V in FP32 (mixed) or FP64. The update, the residual and its
+// norm are one fused FP64 kernel; the norm is the only per-iteration
+// device-to-host transfer (8 bytes).
+//
+// V-cycle on level l with right-hand side f (Sections 2, 2.1, 2.3):
+//   x = omega H_z^{-1} f; (nu_pre - 1) more sweeps;
+//   f_{l+1} = R (f - H x); x_{l+1} = V_{l+1}(f_{l+1}); x += P x_{l+1};
+//   nu_post sweeps; the coarsest level does coarse_sweeps sweeps from zero.
+// The transposed V-cycle reverses these steps (adjoint solve).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mg.h"
+#include "setup.hpp"
+
+namespace {
+
+template <typename T>
+struct Work {
+    T* f = nullptr;     // right-hand side of the level
+    T* xa = nullptr;    // iterate (ping)
+    T* xb = nullptr;    // iterate (pong)
+    T* xbar = nullptr;  // adjoint: transposed iterate
+    T* za = nullptr;    // adjoint: column solves (ping)
+    T* zb = nullptr;    // adjoint: column solves (pong)
+    T* fbar = nullptr;  // adjoint: output of the transposed cycle
+};
+
+struct DevLevel {
+    int nI = 0, nJ = 0, nz = 0;
+    long long plane = 0, n = 0;
+    double *Tlam64 = nullptr, *Tth64 = nullptr, *Tr64 = nullptr, *V64 = nullptr;
+    float *Tlam32 = nullptr, *Tth32 = nullptr, *Tr32 = nullptr;
+    double *M64 = nullptr, *invp64 = nullptr;
+    float *M32 = nullptr, *invp32 = nullptr;
+    // to the next coarser level
+    int *crow_of = nullptr, *prow = nullptr;
+    double* pw64 = nullptr;
+    float* pw32 = nullptr;
+    // from the next finer level
+    int *child_first = nullptr, *child_count = nullptr, *ptrow = nullptr;
+    double* ptw64 = nullptr;
+    float* ptw32 = nullptr;
+    Work<float> w32;
+    Work<double> w64;
+};
+
+struct ProfRec {
+    int cls, level;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct mg_handle {
+    mg_grid grid{};
+    mg_options opt{};
+    mgs::Hierarchy host;
+    std::vector<DevLevel> lv;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    double* u_alt = nullptr;       // FP64 ping-pong partner of the caller's u
+    double* partials = nullptr;
+    double* scalar = nullptr;      // device: reduced value
+    double* host_scalar = nullptr; // pinned host copy
+    int max_partials = 0;
+    bool have32 = false, have64 = false;
+    std::string err;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> events;
+    size_t next_event = 0;
+    double alg_bytes = 0;
+};
+
+namespace {
+
+mg_status fail(mg_handle* h, mg_status s, const char* fmt, ...) {
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->err = buf;
+    }
+    return s;
+}
+
+#define HIP_TRY(h, call)                                                              \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail((h), MG_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define MG_TRY(call)                   \
+    do {                               \
+        mg_status s_ = (call);         \
+        if (s_ != MG_OK) return s_;    \
+    } while (0)
+
+template <typename T>
+mg_status dalloc(mg_handle* h, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, MG_ERR_OOM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    h->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return MG_OK;
+}
+
+template <typename T, typename S>
+mg_status upload(mg_handle* h, T** dst, const std::vector<S>& src) {
+    MG_TRY(dalloc(h, dst, src.size()));
+    std::vector<T> tmp(src.begin(), src.end());
+    if (!tmp.empty())
+        HIP_TRY(h, hipMemcpyAsync(*dst, tmp.data(), tmp.size() * sizeof(T),
+                                  hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+template <typename T>
+mgk::LevelView<T> view(const DevLevel& d);
+
+template <>
+mgk::LevelView<float> view<float>(const DevLevel& d) {
+    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam32, d.Tth32, d.Tr32, d.M32, d.invp32};
+}
+template <>
+mgk::LevelView<double> view<double>(const DevLevel& d) {
+    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam64, d.Tth64, d.Tr64, d.M64, d.invp64};
+}
+
+template <typename T>
+mgk::TransferView<T> xview(const DevLevel& f, const DevLevel& c);
+template <>
+mgk::TransferView<float> xview<float>(const DevLevel& f, const DevLevel& c) {
+    return {c.nI, c.nJ, f.crow_of, f.prow, f.pw32, c.child_first, c.child_count, c.ptrow,
+            c.ptw32};
+}
+template <>
+mgk::TransferView<double> xview<double>(const DevLevel& f, const DevLevel& c) {
+    return {c.nI, c.nJ, f.crow_of, f.prow, f.pw64, c.child_first, c.child_count, c.ptrow,
+            c.ptw64};
+}
+
+template <typename T>
+Work<T>& work(DevLevel& d);
+template <>
+Work<float>& work<float>(DevLevel& d) { return d.w32; }
+template <>
+Work<double>& work<double>(DevLevel& d) { return d.w64; }
+
+template <typename T>
+mg_status ensure_work(mg_handle* h) {
+    bool& have = std::is_same<T, float>::value ? h->have32 : h->have64;
+    if (have) return MG_OK;
+    for (auto& d : h->lv) {
+        Work<T>& w = work<T>(d);
+        for (T** p : {&w.f, &w.xa, &w.xb, &w.xbar, &w.za, &w.zb, &w.fbar})
+            MG_TRY(dalloc(h, p, d.n));
+    }
+    have = true;
+    return MG_OK;
+}
+
+// --- profiling ----------------------------------------------------------------
+hipEvent_t next_event(mg_handle* h) {
+    if (h->next_event == h->events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->events.push_back(e);
+    }
+    return h->events[h->next_event++];
+}
+
+struct Launch {
+    mg_handle* h;
+    ProfRec rec{};
+    bool on = false;
+    Launch(mg_handle* hh, int cls, int level, double bytes) : h(hh) {
+        h->alg_bytes += bytes;
+        // profile 1: finest level only (no events around the short coarse
+        // launches); 2: every launch
+        if (!h->opt.profile || (h->opt.profile == 1 && level != 0)) return;
+        rec.cls = cls;
+        rec.level = level;
+        rec.bytes = bytes;
+        rec.a = next_event(h);
+        rec.b = next_event(h);
+        if (rec.a && rec.b) {
+            on = true;
+            (void)hipEventRecord(rec.a, h->stream);
+        }
+    }
+    ~Launch() {
+        if (!on) return;
+        (void)hipEventRecord(rec.b, h->stream);
+        h->recs.push_back(rec);
+    }
+};
+
+void prof_reset(mg_handle* h) {
+    h->recs.clear();
+    h->next_event = 0;
+    h->alg_bytes = 0;
+}
+
+void prof_collect(mg_handle* h, mg_stats* st) {
+    if (!st) return;
+    for (int c = 0; c < MG_NK; ++c) {
+        st->kern_ms[c] = st->kern_bytes[c] = st->kern_fine_ms[c] = st->kern_fine_bytes[c] = 0;
+        st->kern_launches[c] = st->kern_fine_launches[c] = 0;
+    }
+    for (const ProfRec& r : h->recs) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        st->kern_ms[r.cls] += ms;
+        st->kern_bytes[r.cls] += r.bytes;
+        st->kern_launches[r.cls] += 1;
+        if (r.level == 0) {
+            st->kern_fine_ms[r.cls] += ms;
+            st->kern_fine_bytes[r.cls] += r.bytes;
+            st->kern_fine_launches[r.cls] += 1;
+        }
+    }
+}
+
+mg_status check_launch(mg_handle* h, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(h, MG_ERR_HIP, "launch of %s failed: %s", what,
+                                     hipGetErrorString(e));
+    return MG_OK;
+}
+
+// --- level operations with byte accounting ---------------------------------------
+template <typename T>
+mg_status op_smooth(mg_handle* h, int l, const T* f, const T* xin, T* xout, int cls) {
+    DevLevel& d = h->lv[l];
+    const double bytes = double(d.n) * sizeof(T) * (xin ? 4 : 3);
+    {
+        Launch g(h, cls, l, bytes);
+        mgk::smooth<T>(view<T>(d), f, xin, xout, T(h->opt.omega), h->stream);
+    }
+    return check_launch(h, "smooth");
+}
+
+template <typename T>
+mg_status op_restrict(mg_handle* h, int l, const T* f, const T* x, T* fc) {
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    const double bytes = double(d.n) * sizeof(T) * (x ? 3 : 1) + double(c.n) * sizeof(T);
+    {
+        Launch g(h, MG_K_RESTRICT, l, bytes);
+        mgk::restrict_residual<T>(view<T>(d), xview<T>(d, c), f, x, fc, h->stream);
+    }
+    return check_launch(h, "restrict_residual");
+}
+
+template <typename T>
+mg_status op_prolong(mg_handle* h, int l, const T* xc, T* x) {
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    const double bytes = double(d.n) * sizeof(T) * 2 + double(c.n) * sizeof(T);
+    {
+        Launch g(h, MG_K_PROLONG, l, bytes);
+        mgk::prolong_add<T>(view<T>(d), xview<T>(d, c), xc, x, h->stream);
+    }
+    return check_launch(h, "prolong_add");
+}
+
+// One V-cycle from zero on level l; returns the buffer holding the result.
+template <typename T>
+mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
+    DevLevel& d = h->lv[l];
+    Work<T>& w = work<T>(d);
+    const int last = int(h->lv.size()) - 1;
+    T* cur = w.xa;
+    T* nxt = w.xb;
+    if (l == last) {
+        MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_COARSE));
+        for (int s = 1; s < h->opt.coarse_sweeps; ++s) {
+            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_COARSE));
+            std::swap(cur, nxt);
+        }
+        *result = cur;
+        return MG_OK;
+    }
+    MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH));
+    for (int s = 1; s < h->opt.nu_pre; ++s) {
+        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH));
+        std::swap(cur, nxt);
+    }
+    Work<T>& wc = work<T>(h->lv[l + 1]);
+    MG_TRY(op_restrict<T>(h, l, f, cur, wc.f));
+    T* xc = nullptr;
+    MG_TRY(vcycle<T>(h, l + 1, wc.f, &xc));
+    MG_TRY(op_prolong<T>(h, l, xc, cur));
+    for (int s = 0; s < h->opt.nu_post; ++s) {
+        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH));
+        std::swap(cur, nxt);
+    }
+    *result = cur;
+    return MG_OK;
+}
+
+// Transposed smoother chain of `sweeps` sweeps starting from xbar (no pending
+// column solve). Leaves the last column solve in *zlast (stencil pending) and
+// accumulates fbar. first_sets_fbar: the first kernel writes fbar instead of
+// adding to it.
+template <typename T>
+mg_status chain_T(mg_handle* h, int l, int sweeps, bool first_sets_fbar, T** zlast) {
+    DevLevel& d = h->lv[l];
+    Work<T>& w = work<T>(d);
+    const T om = T(h->opt.omega);
+    T* zin = nullptr;
+    T* zout = w.za;
+    for (int s = 0; s < sweeps; ++s) {
+        const bool acc = !(first_sets_fbar && s == 0);
+        const double bytes = double(d.n) * sizeof(T) * (zin ? 6 : 4);
+        {
+            Launch g(h, MG_K_ADJOINT, l, bytes);
+            mgk::smooth_transpose<T>(view<T>(d), w.xbar, zin, zin ? w.xbar : nullptr, zout,
+                                     w.fbar, om, acc, h->stream);
+        }
+        MG_TRY(check_launch(h, "smooth_transpose"));
+        zin = zout;
+        zout = (zout == w.za) ? w.zb : w.za;
+    }
+    *zlast = zin;
+    return MG_OK;
+}
+
+// Transposed V-cycle on level l applied to g (in work.xbar on entry); the
+// result is left in work.fbar.
+template <typename T>
+mg_status vcycle_T(mg_handle* h, int l) {
+    DevLevel& d = h->lv[l];
+    Work<T>& w = work<T>(d);
+    const int last = int(h->lv.size()) - 1;
+    const T om = T(h->opt.omega);
+    T* z = nullptr;
+    if (l == last) {
+        // (coarse_sweeps - 1) transposed sweeps, then the transposed first
+        // sweep: fbar += omega H_z^{-1} xbar, all as one chain
+        return chain_T<T>(h, l, h->opt.coarse_sweeps, true, &z);
+    }
+    // post-sweeps
+    if (h->opt.nu_post > 0) {
+        MG_TRY(chain_T<T>(h, l, h->opt.nu_post, true, &z));
+        {
+            Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) * 3);
+            mgk::adjoint_stencil<T>(view<T>(d), z, w.xbar, om, h->stream);
+        }
+        MG_TRY(check_launch(h, "adjoint_stencil"));
+    } else {
+        mgk::fill<T>(w.fbar, T(0), d.n, h->stream);
+    }
+    DevLevel& c = h->lv[l + 1];
+    Work<T>& wc = work<T>(c);
+    {
+        Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) + double(c.n) * sizeof(T));
+        mgk::prolong_transpose<T>(view<T>(d), xview<T>(d, c), w.xbar, wc.xbar, h->stream);
+    }
+    MG_TRY(check_launch(h, "prolong_transpose"));
+    MG_TRY(vcycle_T<T>(h, l + 1));
+    {
+        Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) * 5 + double(c.n) * sizeof(T));
+        mgk::inject_residual_adjoint<T>(view<T>(d), xview<T>(d, c), wc.fbar, w.xbar, w.fbar,
+                                        h->stream);
+    }
+    MG_TRY(check_launch(h, "inject_residual_adjoint"));
+    // (nu_pre - 1) transposed pre-sweeps and the transposed first sweep
+    return chain_T<T>(h, l, h->opt.nu_pre, false, &z);
+}
+
+mg_status sync_scalar(mg_handle* h, double* out) {
+    HIP_TRY(h, hipMemcpyAsync(h->host_scalar, h->scalar, sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *out = *h->host_scalar;
+    return MG_OK;
+}
+
+mg_status norm2(mg_handle* h, const double* x, long long n, double* out) {
+    int nb = 0;
+    {
+        Launch g(h, MG_K_OTHER, 0, double(n) * 8);
+        nb = mgk::norm2_partials(x, n, h->partials, h->stream);
+        mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
+    }
+    MG_TRY(check_launch(h, "norm2"));
+    double s2 = 0;
+    MG_TRY(sync_scalar(h, &s2));
+    *out = std::sqrt(s2);
+    return MG_OK;
+}
+
+// FP64 update + residual step; returns ||r||.
+template <typename T>
+mg_status refine_step(mg_handle* h, const double* b, const double* uin, const T* e,
+                      double* uout, T* r, double* rnorm) {
+    DevLevel& d = h->lv[0];
+    const double bytes = double(d.n) * (8 + 8 + 8 + sizeof(T) + (e ? sizeof(T) + 8 : 0));
+    int nb = 0;
+    {
+        Launch g(h, MG_K_RESIDUAL64, 0, bytes);
+        nb = mgk::residual_update<T, T>(view<double>(d), b, uin, e, uout, r, h->partials,
+                                        h->stream);
+    }
+    MG_TRY(check_launch(h, "residual_update"));
+    {
+        Launch g(h, MG_K_OTHER, 0, double(nb) * 8);
+        mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
+    }
+    double s2 = 0;
+    MG_TRY(sync_scalar(h, &s2));
+    *rnorm = std::sqrt(s2);
+    return MG_OK;
+}
+
+// The outer refinement loop in precision T, with the forward (transposed =
+// false) or transposed V-cycle.
+template <typename T>
+mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* st,
+                bool transposed) {
+    MG_TRY(ensure_work<T>(h));
+    DevLevel& d = h->lv[0];
+    Work<T>& w = work<T>(d);
+    auto t0 = std::chrono::steady_clock::now();
+    prof_reset(h);
+    double bnorm = 0;
+    MG_TRY(norm2(h, b, d.n, &bnorm));
+    // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
+    T* r = transposed ? w.xbar : w.f;
+    double rn = 0;
+    MG_TRY(refine_step<T>(h, b, u, nullptr, nullptr, r, &rn));
+    std::vector<double> hist{rn};
+    double* ucur = u;
+    double* unext = h->u_alt;
+    int it = 0;
+    mg_status status = MG_OK;
+    if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
+    while (status == MG_OK) {
+        if (rn <= tol * bnorm) break;
+        if (it >= h->opt.max_iters) {
+            status = MG_ERR_NOT_CONVERGED;
+            break;
+        }
+        const T* e = nullptr;
+        if (!transposed) {
+            T* x = nullptr;
+            MG_TRY(vcycle<T>(h, 0, w.f, &x));
+            e = x;
+        } else {
+            MG_TRY(vcycle_T<T>(h, 0));
+            e = w.fbar;
+        }
+        MG_TRY(refine_step<T>(h, b, ucur, e, unext, r, &rn));
+        std::swap(ucur, unext);
+        ++it;
+        hist.push_back(rn);
+        if (!std::isfinite(rn)) status = MG_ERR_BREAKDOWN;
+    }
+    if (ucur != u) {
+        Launch g(h, MG_K_OTHER, 0, double(d.n) * 16);
+        HIP_TRY(h, hipMemcpyAsync(u, ucur, d.n * sizeof(double), hipMemcpyDeviceToDevice,
+                                  h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    auto t1 = std::chrono::steady_clock::now();
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->iters = it;
+        st->relres = bnorm > 0 ? rn / bnorm : 0.0;
+        for (size_t m = 0; m < hist.size() && m < MG_HIST; ++m) st->res_hist[m] = hist[m];
+        st->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st->levels_used = int(h->lv.size());
+        st->alg_bytes = h->alg_bytes;
+        prof_collect(h, st);
+    }
+    if (status == MG_ERR_BREAKDOWN)
+        return fail(h, status, "non-finite residual norm at iteration %d", it);
+    if (status == MG_ERR_NOT_CONVERGED)
+        h->err = "max_iters reached before the tolerance";
+    return status;
+}
+
+// Device-side coefficients: masses per level, pivots, FP32 copies.
+mg_status set_coeffs(mg_handle* h, const double* alpha) {
+    DevLevel& f = h->lv[0];
+    int nb = mgk::fine_mass(view<double>(f), f.V64, alpha, f.M64, h->partials, h->stream);
+    mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
+    MG_TRY(check_launch(h, "fine_mass"));
+    double bad = 0;
+    MG_TRY(sync_scalar(h, &bad));
+    if (bad != 0)
+        return fail(h, MG_ERR_ARG, "alpha has %.0f values that are not finite and > 0", bad);
+    for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
+        DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+        mgk::restrict_residual<double>(view<double>(d), xview<double>(d, c), d.M64, nullptr,
+                                       c.M64, h->stream);
+        MG_TRY(check_launch(h, "mass aggregation"));
+    }
+    for (auto& d : h->lv) {
+        mgk::pivots(view<double>(d), d.invp64, d.invp32, d.M32, h->stream);
+        MG_TRY(check_launch(h, "pivots"));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return MG_OK;
+}
+
+mg_status build(mg_handle* h, const double* alpha) {
+    std::string e = mgs::plan(h->grid, h->opt.levels, h->opt.semi_threshold, h->host);
+    if (!e.empty()) return fail(h, MG_ERR_ARG, "%s", e.c_str());
+    const size_t L = h->host.levels.size();
+    h->lv.resize(L);
+    for (size_t l = 0; l < L; ++l) {
+        const mgs::Level& s = h->host.levels[l];
+        DevLevel& d = h->lv[l];
+        d.nI = s.nI;
+        d.nJ = s.nJ;
+        d.nz = s.nz;
+        d.plane = (long long)s.nI * s.nJ;
+        d.n = d.plane * s.nz;
+        MG_TRY(upload(h, &d.Tlam64, s.Tlam));
+        MG_TRY(upload(h, &d.Tth64, s.Tth));
+        MG_TRY(upload(h, &d.Tr64, s.Tr));
+        MG_TRY(upload(h, &d.V64, s.V));
+        MG_TRY(upload(h, &d.Tlam32, s.Tlam));
+        MG_TRY(upload(h, &d.Tth32, s.Tth));
+        MG_TRY(upload(h, &d.Tr32, s.Tr));
+        MG_TRY(dalloc(h, &d.M64, d.n));
+        MG_TRY(dalloc(h, &d.invp64, d.n));
+        MG_TRY(dalloc(h, &d.M32, d.n));
+        MG_TRY(dalloc(h, &d.invp32, d.n));
+        if (l + 1 < L) {
+            MG_TRY(upload(h, &d.crow_of, s.crow_of));
+            MG_TRY(upload(h, &d.prow, s.prow));
+            MG_TRY(upload(h, &d.pw64, s.pw));
+            MG_TRY(upload(h, &d.pw32, s.pw));
+        }
+        if (l > 0) {
+            MG_TRY(upload(h, &d.child_first, s.child_first));
+            MG_TRY(upload(h, &d.child_count, s.child_count));
+            MG_TRY(upload(h, &d.ptrow, s.ptrow));
+            MG_TRY(upload(h, &d.ptw64, s.ptw));
+            MG_TRY(upload(h, &d.ptw32, s.ptw));
+        }
+    }
+    DevLevel& f = h->lv[0];
+    h->max_partials = std::max(mgk::blocks_for(f.plane), 8192);
+    MG_TRY(dalloc(h, &h->partials, size_t(h->max_partials)));
+    MG_TRY(dalloc(h, &h->scalar, 1));
+    MG_TRY(dalloc(h, &h->u_alt, f.n));
+    HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, sizeof(double), hipHostMallocDefault));
+    return set_coeffs(h, alpha);
+}
+
+void release(mg_handle* h) {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void* p : h->allocs) (void)hipFree(p);
+    h->allocs.clear();
+    if (h->host_scalar) (void)hipHostFree(h->host_scalar);
+    h->host_scalar = nullptr;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+}
+
+bool shape_ok(const mg_handle* h, int l) { return h && l >= 0 && l < int(h->lv.size()); }
+
+// Cast an FP64 field into a level buffer of precision T (copy for FP64).
+template <typename T>
+void to_level(mg_handle* h, const double* src, T* dst, long long n) {
+    mgk::cast<double, T>(src, dst, n, h->stream);
+}
+template <typename T>
+void from_level(mg_handle* h, const T* src, double* dst, long long n) {
+    mgk::cast<T, double>(src, dst, n, h->stream);
+}
+
+template <typename T>
+mg_status level_sweep(mg_handle* h, int l, const double* f, const double* xin, double* xout) {
+    MG_TRY(ensure_work<T>(h));
+    DevLevel& d = h->lv[l];
+    Work<T>& w = work<T>(d);
+    to_level<T>(h, f, w.f, d.n);
+    if (xin) to_level<T>(h, xin, w.xa, d.n);
+    MG_TRY(op_smooth<T>(h, l, w.f, xin ? w.xa : nullptr, w.xb, MG_K_SMOOTH));
+    from_level<T>(h, w.xb, xout, d.n);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "level_sweep");
+}
+
+template <typename T>
+mg_status level_restrict(mg_handle* h, int l, const double* f, const double* x, double* fc) {
+    MG_TRY(ensure_work<T>(h));
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    Work<T>& w = work<T>(d);
+    Work<T>& wc = work<T>(c);
+    to_level<T>(h, f, w.f, d.n);
+    if (x) to_level<T>(h, x, w.xa, d.n);
+    MG_TRY(op_restrict<T>(h, l, w.f, x ? w.xa : nullptr, wc.f));
+    from_level<T>(h, wc.f, fc, c.n);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "level_residual_restrict");
+}
+
+template <typename T>
+mg_status level_prolong(mg_handle* h, int l, const double* xc, double* x) {
+    MG_TRY(ensure_work<T>(h));
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    Work<T>& w = work<T>(d);
+    Work<T>& wc = work<T>(c);
+    to_level<T>(h, xc, wc.xa, c.n);
+    to_level<T>(h, x, w.xa, d.n);
+    MG_TRY(op_prolong<T>(h, l, wc.xa, w.xa));
+    from_level<T>(h, w.xa, x, d.n);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "level_prolong_add");
+}
+
+template <typename T>
+mg_status one_vcycle(mg_handle* h, const double* f, double* x, bool transposed) {
+    MG_TRY(ensure_work<T>(h));
+    DevLevel& d = h->lv[0];
+    Work<T>& w = work<T>(d);
+    if (!transposed) {
+        to_level<T>(h, f, w.f, d.n);
+        T* out = nullptr;
+        MG_TRY(vcycle<T>(h, 0, w.f, &out));
+        from_level<T>(h, out, x, d.n);
+    } else {
+        to_level<T>(h, f, w.xbar, d.n);
+        MG_TRY(vcycle_T<T>(h, 0));
+        from_level<T>(h, w.fbar, x, d.n);
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "vcycle");
+}
+
+}  // namespace
+
+// --- C ABI ---------------------------------------------------------------------
+extern "C" {
+
+void mg_options_default(mg_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->levels = 0;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->coarse_sweeps = 10;
+    o->max_iters = 100;
+    o->omega = 0.8;
+    o->semi_threshold = 2.0;
+    o->precision = MG_PREC_MIXED;
+    o->stream = nullptr;
+    o->profile = 0;
+}
+
+mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,
+                   mg_handle** out) {
+    if (!out) return MG_ERR_ARG;
+    *out = nullptr;
+    if (!grid || !coeffs || !coeffs->alpha || !opts) return MG_ERR_ARG;
+    std::string e = mgs::validate(*grid, *opts);
+    if (!e.empty()) return MG_ERR_ARG;
+    mg_handle* h = new (std::nothrow) mg_handle();
+    if (!h) return MG_ERR_OOM;
+    h->grid = *grid;
+    h->opt = *opts;
+    h->stream = static_cast<hipStream_t>(opts->stream);
+    mg_status s = build(h, coeffs->alpha);
+    if (s != MG_OK) {
+        std::fprintf(stderr, "mg_setup: %s\n", h->err.c_str());
+        release(h);
+        delete h;
+        return s;
+    }
+    *out = h;
+    return MG_OK;
+}
+
+mg_status mg_update_coeffs(mg_handle* h, const mg_coeffs* coeffs) {
+    if (!h) return MG_ERR_ARG;
+    if (!coeffs || !coeffs->alpha) return fail(h, MG_ERR_ARG, "NULL coefficients");
+    return set_coeffs(h, coeffs->alpha);
+}
+
+mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
+    if (!h) return MG_ERR_ARG;
+    if (!opts) return fail(h, MG_ERR_ARG, "NULL options");
+    std::string e = mgs::validate(h->grid, *opts);
+    if (!e.empty()) return fail(h, MG_ERR_ARG, "%s", e.c_str());
+    if (opts->levels != h->opt.levels || opts->semi_threshold != h->opt.semi_threshold)
+        return fail(h, MG_ERR_ARG, "levels and semi_threshold are fixed at setup");
+    h->opt = *opts;
+    h->stream = static_cast<hipStream_t>(opts->stream);
+    return MG_OK;
+}
+
+static mg_status solve_common(mg_handle* h, const double* rhs, double* u, double tol,
+                              mg_stats* st, bool transposed) {
+    if (!h) return MG_ERR_ARG;
+    if (!rhs || !u) return fail(h, MG_ERR_ARG, "NULL field pointer");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(h, MG_ERR_ARG, "tol must be > 0");
+    if (rhs == u) return fail(h, MG_ERR_ARG, "rhs and solution must not alias");
+    if (h->opt.precision == MG_PREC_FP64)
+        return outer<double>(h, rhs, u, tol, st, transposed);
+    return outer<float>(h, rhs, u, tol, st, transposed);
+}
+
+mg_status mg_solve(mg_handle* h, const double* rhs, double* u, double tol, mg_stats* st) {
+    return solve_common(h, rhs, u, tol, st, false);
+}
+
+mg_status mg_solve_adjoint(mg_handle* h, const double* w, double* lambda, double tol,
+                           mg_stats* st) {
+    return solve_common(h, w, lambda, tol, st, true);
+}
+
+mg_status mg_grad_alpha(mg_handle* h, const double* lambda, const double* u, double* g) {
+    if (!h) return MG_ERR_ARG;
+    if (!lambda || !u || !g) return fail(h, MG_ERR_ARG, "NULL field pointer");
+    DevLevel& d = h->lv[0];
+    mgk::grad_alpha(view<double>(d), d.V64, lambda, u, g, h->stream);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "grad_alpha");
+}
+
+mg_status mg_apply(mg_handle* h, const double* x, double* y) {
+    if (!h) return MG_ERR_ARG;
+    if (!x || !y || x == y) return fail(h, MG_ERR_ARG, "bad field pointers");
+    DevLevel& d = h->lv[0];
+    mgk::apply<double>(view<double>(d), x, nullptr, y, h->stream);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "apply");
+}
+
+mg_status mg_cell_volumes(mg_handle* h, double* V) {
+    if (!h) return MG_ERR_ARG;
+    if (!V) return fail(h, MG_ERR_ARG, "NULL field pointer");
+    DevLevel& d = h->lv[0];
+    mgk::cell_volumes(view<double>(d), d.V64, V, h->stream);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return check_launch(h, "cell_volumes");
+}
+
+mg_status mg_vcycle(mg_handle* h, const double* f, double* x, int32_t transposed) {
+    if (!h) return MG_ERR_ARG;
+    if (!f || !x || f == x) return fail(h, MG_ERR_ARG, "bad field pointers");
+    prof_reset(h);
+    if (h->opt.precision == MG_PREC_FP64) return one_vcycle<double>(h, f, x, transposed != 0);
+    return one_vcycle<float>(h, f, x, transposed != 0);
+}
+
+mg_status mg_level_shape(const mg_handle* h, int32_t l, int32_t shape[3]) {
+    if (!shape_ok(h, l) || !shape) return MG_ERR_ARG;
+    shape[0] = h->lv[l].nI;
+    shape[1] = h->lv[l].nJ;
+    shape[2] = h->lv[l].nz;
+    return MG_OK;
+}
+
+mg_status mg_level_sweep(mg_handle* h, int32_t l, const double* f, const double* x_in,
+                         double* x_out) {
+    if (!h) return MG_ERR_ARG;
+    if (!shape_ok(h, l) || !f || !x_out) return fail(h, MG_ERR_ARG, "bad level or pointer");
+    prof_reset(h);
+    if (h->opt.precision == MG_PREC_FP64) return level_sweep<double>(h, l, f, x_in, x_out);
+    return level_sweep<float>(h, l, f, x_in, x_out);
+}
+
+mg_status mg_level_residual_restrict(mg_handle* h, int32_t l, const double* f,
+                                     const double* x, double* fc) {
+    if (!h) return MG_ERR_ARG;
+    if (!shape_ok(h, l + 1) || l < 0 || !f || !fc)
+        return fail(h, MG_ERR_ARG, "bad level or pointer");
+    prof_reset(h);
+    if (h->opt.precision == MG_PREC_FP64) return level_restrict<double>(h, l, f, x, fc);
+    return level_restrict<float>(h, l, f, x, fc);
+}
+
+mg_status mg_level_prolong_add(mg_handle* h, int32_t l, const double* xc, double* x) {
+    if (!h) return MG_ERR_ARG;
+    if (!shape_ok(h, l + 1) || l < 0 || !xc || !x)
+        return fail(h, MG_ERR_ARG, "bad level or pointer");
+    prof_reset(h);
+    if (h->opt.precision == MG_PREC_FP64) return level_prolong<double>(h, l, xc, x);
+    return level_prolong<float>(h, l, xc, x);
+}
+
+mg_status mg_plan(const mg_grid* grid, const mg_options* opts, int32_t* levels_out,
+                  int32_t* nlon_out, int32_t* nlat_out, int32_t* child_first,
+                  int32_t* child_count, int32_t cap) {
+    if (!grid || !opts || !levels_out || !nlon_out || !nlat_out) return MG_ERR_ARG;
+    if (!mgs::validate(*grid, *opts).empty()) return MG_ERR_ARG;
+    mgs::Hierarchy H;
+    if (!mgs::plan(*grid, opts->levels, opts->semi_threshold, H).empty()) return MG_ERR_ARG;
+    *levels_out = int32_t(H.levels.size());
+    int32_t pos = 0;
+    for (size_t l = 0; l < H.levels.size(); ++l) {
+        nlon_out[l] = H.levels[l].nI;
+        nlat_out[l] = H.levels[l].nJ;
+        if (l == 0) continue;
+        for (int J = 0; J < H.levels[l].nJ; ++J) {
+            if (child_first && child_count) {
+                if (pos >= cap) return MG_ERR_ARG;
+                child_first[pos] = H.levels[l].child_first[J];
+                child_count[pos] = H.levels[l].child_count[J];
+            }
+            ++pos;
+        }
+    }
+    return MG_OK;
+}
+
+mg_status mg_plan_tables(const mg_grid* grid, const mg_options* opts, int32_t l, double* V,
+                         double* Tlam, double* Tth, double* Tr) {
+    if (!grid || !opts) return MG_ERR_ARG;
+    if (!mgs::validate(*grid, *opts).empty()) return MG_ERR_ARG;
+    mgs::Hierarchy H;
+    if (!mgs::plan(*grid, opts->levels, opts->semi_threshold, H).empty()) return MG_ERR_ARG;
+    if (l < 0 || l >= int(H.levels.size())) return MG_ERR_ARG;
+    const mgs::Level& s = H.levels[l];
+    if (V) std::copy(s.V.begin(), s.V.end(), V);
+    if (Tlam) std::copy(s.Tlam.begin(), s.Tlam.end(), Tlam);
+    if (Tth) std::copy(s.Tth.begin(), s.Tth.end(), Tth);
+    if (Tr) std::copy(s.Tr.begin(), s.Tr.end(), Tr);
+    return MG_OK;
+}
+
+void mg_destroy(mg_handle* h) {
+    if (!h) return;
+    release(h);
+    delete h;
+}
+
+const char* mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "ok";
+        case MG_ERR_NOT_CONVERGED: return "not converged";
+        case MG_ERR_ARG: return "invalid argument";
+        case MG_ERR_HIP: return "HIP runtime error";
+        case MG_ERR_OOM: return "out of device memory";
+        case MG_ERR_BREAKDOWN: return "breakdown (non-finite residual)";
+    }
+    return "unknown status";
+}
+
+const char* mg_last_error(const mg_handle* h) { return h ? h->err.c_str() : ""; }
+
+}  // extern "C"

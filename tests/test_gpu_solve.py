@@ -1,0 +1,169 @@
+"""GPU parity of whole V-cycles, solves, the adjoint and the gradient.
+
+  * one FP64 V-cycle (and its transpose) against the oracle: 1e-12 relative;
+  * one FP32 V-cycle against the oracle's FP64 one: 1e-4 relative (2-norm):
+    the FP32 cycle only has to be a good preconditioner for the FP64
+    refinement, which converges as long as this error stays well below
+    1 - rho;
+  * mixed (FP32 V-cycle + FP64 refinement) and FP64 solves: the FP64 residual
+    of the returned u, recomputed by the oracle on the host, meets the
+    tolerance, and u matches the oracle's tightly converged solution;
+  * adjoint: transposed-cycle dot products, lambda and dL/dalpha against the
+    oracle, and central finite differences of L = <w, u>.
+"""
+import numpy as np
+import pytest
+
+import shellgen
+import oracle
+from gpu_util import log, t, n, solver_for, rel_inf, rel2, hierarchy, oracle_solution, opts_of
+
+pytestmark = pytest.mark.gpu
+
+SMALL = shellgen.workload("shell64x32x16")
+MEDIUM = shellgen.workload("shell384x192x70")
+# 96 longitudes: not a multiple of the 64-wide wavefront (ragged tail), and
+# it halves five times before becoming odd
+RAGGED = shellgen.Shell("ragged", 96, 48, 7, stretch=1.2, thickness=0.05)
+DEEP = shellgen.Shell("deep", 96, 48, 70, stretch=1.05)
+
+
+@pytest.mark.parametrize("sh", [SMALL, RAGGED, DEEP], ids=lambda s: s.name)
+def test_vcycle_fp64_and_transpose(sh):
+    a = shellgen.alpha(sh)
+    S = solver_for(sh, a, precision="fp64", nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    f = shellgen.rhs(sh)
+    got = n(S.vcycle(t(f)))
+    ref = oracle.vcycle(L, f, opt)
+    gotT = n(S.vcycle(t(f), transposed=True))
+    refT = oracle.vcycle_T(L, f, opt)
+    log(f"vcycle {sh.name}: {rel_inf(got, ref):.2e} transposed {rel_inf(gotT, refT):.2e}")
+    assert rel_inf(got, ref) < 1e-12
+    assert rel_inf(gotT, refT) < 1e-12
+
+
+@pytest.mark.parametrize("sh", [SMALL, DEEP], ids=lambda s: s.name)
+def test_vcycle_fp32(sh):
+    a = shellgen.alpha(sh)
+    S = solver_for(sh, a, precision="mixed", nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    f = shellgen.rhs(sh)
+    got = n(S.vcycle(t(f)))
+    ref = oracle.vcycle(L, f, opt)
+    gotT = n(S.vcycle(t(f), transposed=True))
+    refT = oracle.vcycle_T(L, f, opt)
+    log(f"vcycle32 {sh.name}: {rel2(got, ref):.2e} transposed {rel2(gotT, refT):.2e}")
+    assert rel2(got, ref) < 1e-4
+    assert rel2(gotT, refT) < 1e-4
+
+
+def test_transposed_vcycle_dot_product_on_gpu():
+    sh = DEEP
+    S = solver_for(sh, shellgen.alpha(sh), precision="fp64", nu_pre=2, nu_post=1)
+    rng = np.random.default_rng(21)
+    x, y = rng.standard_normal(sh.shape), rng.standard_normal(sh.shape)
+    lhs = np.vdot(n(S.vcycle(t(x))), y)
+    rhs = np.vdot(x, n(S.vcycle(t(y), transposed=True)))
+    log(f"dot test {lhs:.15e} {rhs:.15e}")
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("sh", [SMALL, RAGGED, MEDIUM], ids=lambda s: s.name)
+def test_solve_matches_oracle(sh, prec):
+    a = shellgen.alpha(sh)
+    b = shellgen.rhs(sh)
+    S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    L = hierarchy(sh)
+    uref, stref = oracle_solution(sh)
+    for tol in (sh.tol, 1e-10):
+        u, st = S.solve(t(b), tol=tol)
+        u = n(u)
+        rel_res = np.linalg.norm((b - oracle.apply(L[0], u)).ravel()) / np.linalg.norm(b)
+        fwd = rel2(u, uref)
+        log(f"solve {sh.name} {prec} tol={tol:g}: iters {st.iters} gpu relres {st.relres:.2e} "
+            f"host relres {rel_res:.2e} fwd err {fwd:.2e} (oracle iters {stref['iters']})")
+        assert st.relres <= tol
+        assert rel_res <= tol * 1.01
+        assert st.iters <= stref["iters"] + 2
+    # at relative residual 1e-10 the solution matches the oracle to 1e-8
+    assert fwd < 1e-8
+
+
+def test_solve_edge_cases():
+    # single-level hierarchy, one layer, nonzero initial guess, determinism
+    for sh in [shellgen.Shell("t1", 4, 2, 1, stretch=1.0),
+               shellgen.Shell("t2", 6, 4, 2, stretch=1.0),
+               shellgen.Shell("t3", 2, 2, 3)]:
+        a, b = shellgen.alpha(sh), shellgen.rhs(sh)
+        S = solver_for(sh, a, precision="mixed")
+        u, st = S.solve(t(b), tol=1e-10)
+        L = oracle.build_hierarchy(sh, a)
+        ud = np.linalg.solve(oracle.assemble(L[0]).toarray(), b.ravel()).reshape(sh.shape)
+        log(f"edge {sh.name}: iters {st.iters} relres {st.relres:.2e} err {rel2(n(u), ud):.2e}")
+        assert rel2(n(u), ud) < 1e-8
+    sh = RAGGED
+    a, b = shellgen.alpha(sh), shellgen.rhs(sh)
+    S = solver_for(sh, a)
+    u1, s1 = S.solve(t(b), tol=1e-9)
+    u2, s2 = S.solve(t(b), tol=1e-9)
+    assert np.array_equal(n(u1), n(u2)) and s1.res_hist == s2.res_hist
+    # warm start from the converged answer: zero iterations
+    u3, s3 = S.solve(t(b), tol=1e-9, u0=u1)
+    assert s3.iters == 0
+    # rhs = 0 gives u = 0 immediately
+    u4, s4 = S.solve(t(np.zeros(sh.shape)), tol=1e-9)
+    assert s4.iters == 0 and float(n(u4).max()) == 0.0
+
+
+def test_adjoint_and_gradient_match_oracle():
+    sh = RAGGED
+    a, b, w = shellgen.alpha(sh), shellgen.rhs(sh), shellgen.weights(sh)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    u_ref, _ = oracle.solve(L, b, opt, tol=1e-13)
+    lam_ref, _ = oracle.solve_adjoint(L, w, opt, tol=1e-13)
+    g_ref = oracle.grad_alpha(L, lam_ref, u_ref)
+    for prec in ("fp64", "mixed"):
+        S = solver_for(sh, a, precision=prec)
+        u, _ = S.solve(t(b), tol=1e-12)
+        lam, st = S.solve_adjoint(t(w), tol=1e-12)
+        g = n(S.grad_alpha(lam, u))
+        log(f"adjoint {prec}: iters {st.iters} lam err {rel2(n(lam), lam_ref):.2e} "
+            f"grad err {rel2(g, g_ref):.2e}")
+        assert rel2(n(lam), lam_ref) < 1e-9
+        assert rel2(g, g_ref) < 1e-9
+
+
+def test_autograd_finite_differences_small():
+    import torch
+    from paper_2307_04528_amd import mg_solve
+    sh = RAGGED
+    a, b, w = shellgen.alpha(sh), shellgen.rhs(sh), shellgen.weights(sh)
+    S = solver_for(sh, a, precision="fp64")
+    at = t(a).requires_grad_(True)
+    bt = t(b).requires_grad_(True)
+    u = mg_solve(bt, at, S, 1e-13)
+    loss = (t(w) * u).sum()
+    loss.backward()
+    ga, gb = n(at.grad), n(bt.grad)
+    S2 = solver_for(sh, a, precision="fp64", max_iters=40)
+
+    def L_of(alpha, rhs):
+        S2.update_alpha(t(alpha))
+        uu, _ = S2.solve(t(rhs), tol=1e-14)
+        return float(np.vdot(w, n(uu)))
+
+    h = 1e-6
+    for m in range(4):
+        d = shellgen.fd_direction(sh, m)
+        fd_b = (L_of(a, b + h * d) - L_of(a, b - h * d)) / (2 * h)
+        fd_a = (L_of(a * (1 + h * d), b) - L_of(a * (1 - h * d), b)) / (2 * h)
+        an_b, an_a = float(np.vdot(gb, d)), float(np.vdot(ga, a * d))
+        log(f"fd m={m}: b {fd_b:.12e} vs {an_b:.12e}; alpha {fd_a:.12e} vs {an_a:.12e}")
+        assert fd_b == pytest.approx(an_b, rel=1e-6)
+        assert fd_a == pytest.approx(an_a, rel=1e-6)
+    del torch

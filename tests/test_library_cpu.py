@@ -1,0 +1,86 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host-side planning (hierarchy sizes, coarsening maps and
+FP64 geometry tables) equals the oracle's independently computed ones.
+No GPU call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import shellgen
+from conftest import ROOT, ensure_library
+from oracle import build_hierarchy
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    path = ensure_library()
+    lib = C.CDLL(path)
+    names = _declared()
+    assert "mg_setup" in names and "mg_solve" in names and "mg_solve_adjoint" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2307_04528_amd import _lib
+    assert sorted(_lib.EXPORTED) == names
+
+
+SHELLS = [
+    shellgen.Shell("a", 8, 4, 3, stretch=1.1),
+    shellgen.Shell("b", 16, 8, 5, stretch=1.2),
+    shellgen.Shell("c", 64, 32, 16, stretch=1.1),
+    shellgen.Shell("d", 100, 50, 7, stretch=1.0),
+    shellgen.Shell("e", 384, 192, 4, stretch=1.05),
+    shellgen.Shell("f", 1024, 768, 2, stretch=1.07),
+    shellgen.Shell("g", 6, 2, 1),
+]
+
+
+def _kw(sh):
+    return dict(radius=sh.radius, thickness=sh.thickness, stretch=sh.stretch, K=sh.K)
+
+
+@pytest.mark.parametrize("sh", SHELLS, ids=lambda s: f"{s.nlon}x{s.nlat}x{s.nlev}")
+@pytest.mark.parametrize("levels", [0, 4])
+def test_host_plan_matches_oracle(sh, levels):
+    ensure_library()
+    from paper_2307_04528_amd import mg_plan
+    plan = mg_plan(sh.nlon, sh.nlat, sh.nlev, levels=levels, **_kw(sh))
+    L = build_hierarchy(sh, np.ones(sh.shape), levels=levels)
+    assert plan["sizes"] == [(l.nlon, l.nlat) for l in L]
+    for l in range(1, len(L)):
+        assert plan["child_first"][l - 1] == list(L[l].child_first)
+        assert plan["child_count"][l - 1] == list(L[l].child_count)
+
+
+@pytest.mark.parametrize("sh", SHELLS[:5], ids=lambda s: f"{s.nlon}x{s.nlat}x{s.nlev}")
+def test_host_tables_match_oracle(sh):
+    ensure_library()
+    from paper_2307_04528_amd import mg_plan_tables
+    L = build_hierarchy(sh, np.ones(sh.shape))
+    for l, lev in enumerate(L):
+        V, Tl, Tt, Tr = mg_plan_tables(l, sh.nlon, sh.nlat, sh.nlev, **_kw(sh))
+        np.testing.assert_allclose(V, lev.V, rtol=1e-11)
+        np.testing.assert_allclose(Tl, lev.Tlam, rtol=1e-11)
+        np.testing.assert_allclose(Tt, lev.Tth, rtol=1e-11, atol=1e-15 * lev.Tth.max())
+        np.testing.assert_allclose(Tr, lev.Tr, rtol=1e-11)
+
+
+@pytest.mark.parametrize("bad", [dict(nlon=7), dict(nlat=5), dict(nlon=0), dict(nlev=0),
+                                 dict(nlev=129), dict(thickness=-1.0), dict(K=0.0),
+                                 dict(omega=2.5), dict(nu_pre=0), dict(max_iters=500),
+                                 dict(semi_threshold=0.0)])
+def test_host_argument_validation(bad):
+    ensure_library()
+    from paper_2307_04528_amd import mg_plan
+    from paper_2307_04528_amd._lib import MGError
+    kw = dict(nlon=16, nlat=8, nlev=4)
+    kw.update(bad)
+    with pytest.raises(MGError):
+        mg_plan(**kw)
