@@ -80,9 +80,10 @@ typedef struct {
 
 /* Solver options (fill with mg_options_default, then override).
  * levels        : 0 = automatic (coarsen until every row of the coarsest
- *                 level has anisotropy <= semi_threshold, or until the
- *                 number of longitudes is odd); n > 0 = at most n levels
- *                 (the paper's shallow hierarchy uses 4).
+ *                 level has anisotropy <= semi_threshold, until the number
+ *                 of longitudes is odd, or until a coarser level would have
+ *                 fewer than 4 longitudes); n > 0 = at most n levels (the
+ *                 paper's shallow hierarchy uses 4).
  * nu_pre/nu_post: smoother sweeps before/after the coarse correction
  *                 (nu_pre >= 1; the first pre-sweep starts from zero).
  * coarse_sweeps : smoother sweeps from zero on the coarsest level (>= 1).
@@ -145,7 +146,7 @@ typedef struct {
 
 typedef struct mg_handle mg_handle;
 
-/* Fill *opts with defaults: levels 0 (auto), V(2,2), 10 coarse sweeps,
+/* Fill *opts with defaults: levels 0 (auto), V(2,2), 20 coarse sweeps,
  * max_iters 100, omega 0.8, semi_threshold 2, MG_PREC_MIXED, default stream,
  * no profiling. */
 void mg_options_default(mg_options* opts);

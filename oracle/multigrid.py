@@ -14,7 +14,10 @@ Paper steps followed:
     correction and smooths again. Each outer iteration should reduce the
     residual norm ||b - Hu|| by about an order of magnitude.
   * Section 2.3: the coarsest grid is handled by "a simple iterative method";
-    here n_c smoother sweeps from zero.
+    here n_c smoother sweeps from zero (n_c = 20 by default: on the
+    1024x768x70 shell 10 sweeps leave the coarse error large enough to raise
+    the V-cycle's convergence factor from about 0.27 to 0.45, while 40 sweeps
+    do no better than 20).
 
 Readings where the paper is silent:
   * restriction R sums the residuals of the children cells (the residual is
@@ -52,7 +55,7 @@ class Options:
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
-    coarse_sweeps: int = 10
+    coarse_sweeps: int = 20
     max_iters: int = 100
 
 

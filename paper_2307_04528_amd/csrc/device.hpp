@@ -1,0 +1,162 @@
+// Device-side helpers shared by the kernel files (gfx950).
+//
+// Mapping. Kernels that walk a vertical column (the Thomas solves, and the
+// stencils that need the layers above and below) use one lane per column
+// (I, J); a wavefront covers 64 consecutive longitudes of a row, so every
+// layer k is one coalesced 256 B (FP32) / 512 B (FP64) access per wavefront.
+// Kernels with no sequential dependence in k use one lane per cell.
+//
+// Latency. A column kernel is a chain of nz dependent steps. The layer loop is
+// fully unrolled over a compile-time bucket NZ >= nz and every load is
+// unconditional: layer indices are clamped to nz-1, neighbour offsets at the
+// poles are clamped to the cell itself (their coefficient in the tables is
+// exactly 0), and the top/bottom vertical coefficients are 0; only stores are
+// guarded. The Thomas sweeps prefetch explicitly: the loads of the next chunk
+// of D layers are issued before the current chunk is solved, with scheduling
+// barriers so the compiler neither serialises them nor hoists everything
+// (which would spill the per-column registers).
+//
+// Addressing. Each layer of a per-cell array is a wave-uniform base held in
+// scalar registers plus a 32-bit per-lane byte offset (global_load with a
+// scalar base). Coefficient tables are read through the constant address
+// space; where every wavefront lies inside one latitude row (nI a multiple of
+// 64) their index is wave-uniform and they become scalar loads.
+//
+// L2 locality. The hardware hands block b to XCD b % 8; blocks are remapped
+// so that each XCD works on one contiguous range of columns, and the
+// latitude neighbours that a stencil re-reads come from the same L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace mgk {
+namespace dev {
+
+__device__ __forceinline__ uint32_t logical_block() {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb >> 3, r = nb & 7, x = b & 7, s = b >> 3;
+    return x * q + (x < r ? x : r) + s;
+}
+
+__device__ __forceinline__ uint32_t global_index() {
+    return logical_block() * blockDim.x + threadIdx.x;
+}
+
+__device__ __forceinline__ int clampk(int k, int nz) { return k < nz ? k : nz - 1; }
+
+// Element offsets (within one layer) of a column and of its four horizontal
+// neighbours; at a pole the missing neighbour is the cell itself. ROWU: every
+// wavefront lies inside one latitude row, so the row index is wave-uniform.
+struct Nb {
+    uint32_t c, w, e, s, n;
+    int J;
+};
+
+template <bool ROWU>
+__device__ __forceinline__ Nb neighbours(uint32_t col, int nI, int nJ) {
+    int J = int(col / uint32_t(nI));
+    if constexpr (ROWU) J = __builtin_amdgcn_readfirstlane(J);
+    const int i = int(col) - J * nI;
+    Nb b;
+    b.J = J;
+    b.c = col;
+    b.w = (i == 0) ? col + uint32_t(nI - 1) : col - 1u;
+    b.e = (i == nI - 1) ? col - uint32_t(nI - 1) : col + 1u;
+    b.s = (J > 0) ? col - uint32_t(nI) : col;
+    b.n = (J < nJ - 1) ? col + uint32_t(nI) : col;
+    return b;
+}
+
+// The same offsets in bytes for element type T (a layer of any per-cell
+// array is < 4 GiB).
+template <typename T>
+struct NbB {
+    uint32_t c, w, e, s, n;
+    int J;
+    __device__ __forceinline__ explicit NbB(const Nb& b)
+        : c(b.c * uint32_t(sizeof(T))), w(b.w * uint32_t(sizeof(T))),
+          e(b.e * uint32_t(sizeof(T))), s(b.s * uint32_t(sizeof(T))),
+          n(b.n * uint32_t(sizeof(T))), J(b.J) {}
+};
+
+// Wave-uniform base of layer kk (layer stride Pb bytes), pinned to scalar
+// registers, as a global-address-space pointer.
+__device__ __forceinline__ uint64_t uniform64(uint64_t p) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(p));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(p >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+typedef const __attribute__((address_space(1))) char* gcptr;
+typedef __attribute__((address_space(1))) char* gptr;
+
+template <typename T>
+__device__ __forceinline__ gcptr layer(const T* a, int kk, uint64_t Pb) {
+    return (gcptr)(uniform64(reinterpret_cast<uint64_t>(a) + uint64_t(kk) * Pb));
+}
+template <typename T>
+__device__ __forceinline__ gptr layer_w(T* a, int kk, uint64_t Pb) {
+    return (gptr)(uniform64(reinterpret_cast<uint64_t>(a) + uint64_t(kk) * Pb));
+}
+template <typename T>
+__device__ __forceinline__ T ldb(gcptr base, uint32_t boff) {
+    return *(const __attribute__((address_space(1))) T*)(base + boff);
+}
+template <typename T>
+__device__ __forceinline__ void stb(gptr base, uint32_t boff, T v) {
+    *(__attribute__((address_space(1))) T*)(base + boff) = v;
+}
+
+// Read-only coefficient tables through the constant address space.
+template <typename T>
+__device__ __forceinline__ T tab(const T* p, int idx) {
+    return ((const __attribute__((address_space(4))) T*)p)[idx];
+}
+
+template <typename T>
+__device__ __forceinline__ void block_sum_to(T v, T* out) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __shared__ T red[1024 / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = 0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) t += red[w];
+        *out = t;
+    }
+}
+
+// Horizontal part of H at one cell in difference form:
+// Tlam (2xc - xw - xe) + Ts (xc - xs) + Tn (xc - xn).
+template <typename T>
+__device__ __forceinline__ T hdiff(T tl, T ts, T tn, T xc, T xw, T xe, T xs, T xn) {
+    return tl * ((xc - xw) + (xc - xe)) + ts * (xc - xs) + tn * (xc - xn);
+}
+
+}  // namespace dev
+
+inline int grid_stride_blocks(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    return int(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+// Dispatch the layer-count bucket NZ >= nz at compile time.
+template <typename F>
+void with_nz(int nz, F&& fn) {
+    if (nz <= 16) fn(std::integral_constant<int, 16>{});
+    else if (nz <= 32) fn(std::integral_constant<int, 32>{});
+    else if (nz <= 72) fn(std::integral_constant<int, 72>{});
+    else fn(std::integral_constant<int, 128>{});
+}
+
+// Levels with fewer columns than this cannot fill the GPU with one lane per
+// column; their Thomas sweeps prefetch deeper (latency rather than
+// bandwidth bound).
+constexpr long long kSmallLevelColumns = 1LL << 15;
+
+}  // namespace mgk

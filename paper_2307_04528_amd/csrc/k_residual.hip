@@ -1,0 +1,275 @@
+// Operator apply, the FP64 refinement step (update + residual + norm), the
+// deterministic reductions, and the setup / elementwise kernels.
+//
+// H is always evaluated in difference form (paper Section 2: Hu with H a
+// Laplacian-like matrix):
+//   (H x)_c = sum_faces T_f (x_c - x_nb) + M_c x_c.
+#include "device.hpp"
+
+namespace mgk {
+
+namespace {
+using namespace dev;
+
+// y = H x (HAS_F = false) or y = f - H x, one lane per cell.
+template <typename T, bool HAS_F>
+__global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __restrict__ x,
+                                                  const T* __restrict__ f, T* __restrict__ y,
+                                                  uint32_t n) {
+    const uint32_t t = global_index();
+    if (t >= n) return;
+    const uint32_t P = uint32_t(L.plane);
+    const int nJ = L.nJ, nz = L.nz;
+    const int k = int(t / P);
+    const Nb b = neighbours<false>(t - uint32_t(k) * P, L.nI, nJ);
+    const T* xk = x + size_t(k) * P;
+    const T xc = xk[b.c];
+    const T xm = x[size_t(k > 0 ? k - 1 : 0) * P + b.c];
+    const T xp = x[size_t(k + 1 < nz ? k + 1 : k) * P + b.c];
+    const T h = L.M[t] * xc +
+                hdiff(L.Tlam[k * nJ + b.J], L.Tth[k * (nJ + 1) + b.J],
+                      L.Tth[k * (nJ + 1) + b.J + 1], xc, xk[b.w], xk[b.e], xk[b.s], xk[b.n]) +
+                L.Tr[k * nJ + b.J] * (xc - xm) + L.Tr[(k + 1) * nJ + b.J] * (xc - xp);
+    y[t] = HAS_F ? f[t] - h : h;
+}
+
+// FP64 refinement step on the finest level, one lane per column:
+//   unew = uin + e (HAS_E; written to uout), r = b - H unew (stored as TR),
+//   per-block partial sums of r^2 in FP64.
+template <typename TE, typename TR, int NZ, bool HAS_E, bool ROWU>
+__global__ __launch_bounds__(kBlock) void k_residual_update(
+    LevelView<double> L, const double* __restrict__ bv, const double* __restrict__ uin,
+    const TE* __restrict__ e, double* __restrict__ uout, TR* __restrict__ r,
+    double* __restrict__ partials) {
+    const uint32_t col = global_index();
+    double acc = 0;
+    if (col < uint32_t(L.plane)) {
+        const Nb nb = neighbours<ROWU>(col, L.nI, L.nJ);
+        const NbB<double> b8(nb);
+        const NbB<TE> be(nb);
+        const NbB<TR> br(nb);
+        const int nJ = L.nJ, nz = L.nz;
+        const uint64_t P8 = uint64_t(L.plane) * 8, PE = uint64_t(L.plane) * sizeof(TE),
+                       PR = uint64_t(L.plane) * sizeof(TR);
+        auto un = [&](int kk, uint32_t o8, uint32_t oe) -> double {
+            double v = ldb<double>(layer(uin, kk, P8), o8);
+            if constexpr (HAS_E) v += double(ldb<TE>(layer(e, kk, PE), oe));
+            return v;
+        };
+        double um = 0, uc = un(0, b8.c, be.c);
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+            const int kk = clampk(k, nz), kp = clampk(k + 1, nz);
+            const double up = un(kp, b8.c, be.c);
+            const double h =
+                ldb<double>(layer(L.M, kk, P8), b8.c) * uc +
+                hdiff(tab(L.Tlam, kk * nJ + nb.J), tab(L.Tth, kk * (nJ + 1) + nb.J),
+                      tab(L.Tth, kk * (nJ + 1) + nb.J + 1), uc, un(kk, b8.w, be.w),
+                      un(kk, b8.e, be.e), un(kk, b8.s, be.s), un(kk, b8.n, be.n)) +
+                tab(L.Tr, kk * nJ + nb.J) * (uc - um) + tab(L.Tr, (kk + 1) * nJ + nb.J) * (uc - up);
+            const double rv = ldb<double>(layer(bv, kk, P8), b8.c) - h;
+            if (k < nz) {
+                if constexpr (HAS_E) stb<double>(layer_w(uout, kk, P8), b8.c, uc);
+                stb<TR>(layer_w(r, kk, PR), br.c, TR(rv));
+                acc += rv * rv;
+            }
+            um = uc;
+            uc = up;
+        }
+    }
+    block_sum_to(acc, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm2_partials(const double* __restrict__ x,
+                                                           long long n,
+                                                           double* __restrict__ partials) {
+    double acc = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+        acc += x[t] * x[t];
+    block_sum_to(acc, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
+                                                       double* __restrict__ out) {
+    __shared__ double red[1024];
+    double acc = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) acc += p[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Setup: M = alpha V on the finest level; counts alpha values that are not
+// finite and > 0.
+__global__ __launch_bounds__(kBlock) void k_fine_mass(LevelView<double> L,
+                                                      const double* __restrict__ V,
+                                                      const double* __restrict__ alpha,
+                                                      double* __restrict__ M, long long n,
+                                                      double* __restrict__ partials) {
+    double bad = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const int k = int(t / L.plane);
+        const int J = int((t - k * L.plane) / L.nI);
+        const double a = alpha[t];
+        if (!(a > 0.0) || !isfinite(a)) bad += 1.0;
+        M[t] = a * V[k * L.nJ + J];
+    }
+    block_sum_to(bad, partials + blockIdx.x);
+}
+
+// Setup: row-sum form of the Thomas pivots of H_z, per column:
+//   mt_k = M_k + 2 Tlam + Tth(south) + Tth(north)
+//   g_0 = mt_0, g_k = mt_k + Tr_k g_{k-1} / (Tr_k + g_{k-1}),  p_k = Tr_{k+1} + g_k,
+// the textbook pivots D_k - Tr_k^2 / p_{k-1} without the cancellation.
+__global__ __launch_bounds__(kBlock) void k_pivots(LevelView<double> L,
+                                                   double* __restrict__ invp64,
+                                                   float* __restrict__ invp32,
+                                                   float* __restrict__ M32) {
+    const uint32_t col = global_index();
+    if (col >= uint32_t(L.plane)) return;
+    const int J = int(col / uint32_t(L.nI)), nJ = L.nJ;
+    double g = 0;
+    for (int k = 0; k < L.nz; ++k) {
+        const size_t o = size_t(k) * L.plane + col;
+        const double mt = L.M[o] + 2.0 * L.Tlam[k * nJ + J] + L.Tth[k * (nJ + 1) + J] +
+                          L.Tth[k * (nJ + 1) + J + 1];
+        const double trb = L.Tr[k * nJ + J];
+        g = (k == 0) ? mt : mt + trb * g / (trb + g);
+        const double ip = 1.0 / (L.Tr[(k + 1) * nJ + J] + g);
+        invp64[o] = ip;
+        invp32[o] = float(ip);
+        M32[o] = float(L.M[o]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_alpha(LevelView<double> L,
+                                                       const double* __restrict__ V,
+                                                       const double* __restrict__ lam,
+                                                       const double* __restrict__ u,
+                                                       double* __restrict__ g, uint32_t n) {
+    const uint32_t t = global_index();
+    if (t >= n) return;
+    const uint32_t P = uint32_t(L.plane);
+    const int k = int(t / P);
+    const int J = int((t - uint32_t(k) * P) / uint32_t(L.nI));
+    g[t] = -lam[t] * V[k * L.nJ + J] * u[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_volumes(LevelView<double> L,
+                                                         const double* __restrict__ V,
+                                                         double* __restrict__ out, uint32_t n) {
+    const uint32_t t = global_index();
+    if (t >= n) return;
+    const uint32_t P = uint32_t(L.plane);
+    const int k = int(t / P);
+    const int J = int((t - uint32_t(k) * P) / uint32_t(L.nI));
+    out[t] = V[k * L.nJ + J];
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(kBlock) void k_cast(const TA* __restrict__ in, TB* __restrict__ out,
+                                                 long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+        out[t] = TB(in[t]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ out, T v, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+        out[t] = v;
+}
+
+}  // namespace
+
+template <typename T>
+void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
+    const long long n = L.plane * L.nz;
+    if (f) k_apply<T, true><<<blocks_for(n), kBlock, 0, s>>>(L, x, f, y, uint32_t(n));
+    else k_apply<T, false><<<blocks_for(n), kBlock, 0, s>>>(L, x, f, y, uint32_t(n));
+}
+
+template <typename TE, typename TR>
+int residual_update(const LevelView<double>& L, const double* b, const double* uin,
+                    const TE* e, double* uout, TR* r, double* partials, hipStream_t s) {
+    const int nb = blocks_for(L.plane);
+    const bool rowu = L.nI % 64 == 0;
+    with_nz(L.nz, [&](auto nzc) {
+        constexpr int NZ = decltype(nzc)::value;
+#define MG_RES_LAUNCH(HE, RU) \
+    k_residual_update<TE, TR, NZ, HE, RU><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r, partials)
+        if (e) { if (rowu) MG_RES_LAUNCH(true, true); else MG_RES_LAUNCH(true, false); }
+        else { if (rowu) MG_RES_LAUNCH(false, true); else MG_RES_LAUNCH(false, false); }
+#undef MG_RES_LAUNCH
+    });
+    return nb;
+}
+
+int norm2_partials(const double* x, long long n, double* partials, hipStream_t s) {
+    const int nb = grid_stride_blocks(n);
+    k_norm2_partials<<<nb, kBlock, 0, s>>>(x, n, partials);
+    return nb;
+}
+
+void sum_partials(const double* partials, int n, double* out, hipStream_t s) {
+    k_sum_partials<<<1, 1024, 0, s>>>(partials, n, out);
+}
+
+int fine_mass(const LevelView<double>& L, const double* V, const double* alpha, double* M,
+              double* partials, hipStream_t s) {
+    const long long n = L.plane * L.nz;
+    const int nb = grid_stride_blocks(n);
+    k_fine_mass<<<nb, kBlock, 0, s>>>(L, V, alpha, M, n, partials);
+    return nb;
+}
+
+void pivots(const LevelView<double>& L, double* invp64, float* invp32, float* M32,
+            hipStream_t s) {
+    k_pivots<<<blocks_for(L.plane), kBlock, 0, s>>>(L, invp64, invp32, M32);
+}
+
+void grad_alpha(const LevelView<double>& L, const double* V, const double* lam,
+                const double* u, double* g, hipStream_t s) {
+    const long long n = L.plane * L.nz;
+    k_grad_alpha<<<blocks_for(n), kBlock, 0, s>>>(L, V, lam, u, g, uint32_t(n));
+}
+
+void cell_volumes(const LevelView<double>& L, const double* V, double* out, hipStream_t s) {
+    const long long n = L.plane * L.nz;
+    k_cell_volumes<<<blocks_for(n), kBlock, 0, s>>>(L, V, out, uint32_t(n));
+}
+
+template <typename TA, typename TB>
+void cast(const TA* in, TB* out, long long n, hipStream_t s) {
+    k_cast<TA, TB><<<grid_stride_blocks(n), kBlock, 0, s>>>(in, out, n);
+}
+
+template <typename T>
+void fill(T* out, T v, long long n, hipStream_t s) {
+    k_fill<T><<<grid_stride_blocks(n), kBlock, 0, s>>>(out, v, n);
+}
+
+template void apply<float>(const LevelView<float>&, const float*, const float*, float*,
+                           hipStream_t);
+template void apply<double>(const LevelView<double>&, const double*, const double*, double*,
+                            hipStream_t);
+template int residual_update<float, float>(const LevelView<double>&, const double*,
+                                           const double*, const float*, double*, float*,
+                                           double*, hipStream_t);
+template int residual_update<double, double>(const LevelView<double>&, const double*,
+                                             const double*, const double*, double*,
+                                             double*, double*, hipStream_t);
+template void cast<double, float>(const double*, float*, long long, hipStream_t);
+template void cast<float, double>(const float*, double*, long long, hipStream_t);
+template void cast<double, double>(const double*, double*, long long, hipStream_t);
+template void fill<float>(float*, float, long long, hipStream_t);
+template void fill<double>(double*, double, long long, hipStream_t);
+
+}  // namespace mgk

@@ -49,6 +49,16 @@ template <typename T>
 void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
             hipStream_t s);
 
+// The whole coarsest-level solve in one launch (one block): `sweeps` sweeps
+// from zero, ping-ponging between xa and xb. Returns 0 if the result is in
+// xa, 1 if in xb. Meant for levels of at most kCoarseSolveColumns columns;
+// levels of at most kBlock columns whose data fit in max_lds bytes of LDS
+// (three per-cell arrays) run entirely in LDS.
+constexpr long long kCoarseSolveColumns = 4096;
+template <typename T>
+int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int sweeps,
+                 size_t max_lds, hipStream_t s);
+
 // fc = R (f - H x) (sum over children), or R f when x == nullptr.
 template <typename T>
 void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T* f,

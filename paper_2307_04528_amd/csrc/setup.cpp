@@ -20,6 +20,7 @@ namespace mgs {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kMinLongitudes = 4;
 
 void vertical(const mg_grid& g, std::vector<double>& re, std::vector<double>& rc) {
     const int nz = g.nlev;
@@ -215,7 +216,10 @@ std::string plan(const mg_grid& g, int levels, double threshold, Hierarchy& H) {
         Level& cur = H.levels.back();
         if (levels > 0 && int(H.levels.size()) >= levels) break;
         if (levels == 0 && cur.max_anisotropy <= threshold) break;
-        if (cur.nI % 2 != 0 || cur.nI < 2) break;
+        // halve the longitudes only while the count is even, and never below
+        // kMinLongitudes cells around a circle (wider cells make the
+        // cell-centred fluxes meaningless and the coarse correction harmful)
+        if (cur.nI % 2 != 0 || cur.nI / 2 < kMinLongitudes) break;
         Level c;
         group_rows(cur, threshold, c.child_first, c.child_count);
         c.nI = cur.nI / 2;

@@ -79,6 +79,7 @@ struct mg_handle {
     double* scalar = nullptr;      // device: reduced value
     double* host_scalar = nullptr; // pinned host copy
     int max_partials = 0;
+    size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
     bool have32 = false, have64 = false;
     std::string err;
     std::vector<ProfRec> recs;
@@ -298,6 +299,19 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     T* cur = w.xa;
     T* nxt = w.xb;
     if (l == last) {
+        if (d.plane <= mgk::kCoarseSolveColumns) {
+            // all coarse sweeps in one single-block launch
+            int where = 0;
+            {
+                Launch g(h, MG_K_COARSE, l,
+                         double(d.n) * sizeof(T) * (3.0 + 4.0 * (h->opt.coarse_sweeps - 1)));
+                where = mgk::coarse_solve<T>(view<T>(d), f, cur, nxt, T(h->opt.omega),
+                                             h->opt.coarse_sweeps, h->max_lds, h->stream);
+            }
+            MG_TRY(check_launch(h, "coarse_solve"));
+            *result = where == 0 ? cur : nxt;
+            return MG_OK;
+        }
         MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_COARSE));
         for (int s = 1; s < h->opt.coarse_sweeps; ++s) {
             MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_COARSE));
@@ -574,6 +588,14 @@ mg_status build(mg_handle* h, const double* alpha) {
     MG_TRY(dalloc(h, &h->scalar, 1));
     MG_TRY(dalloc(h, &h->u_alt, f.n));
     HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, sizeof(double), hipHostMallocDefault));
+    {
+        int dev = 0, lds = 0;
+        HIP_TRY(h, hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess && lds > 0)
+            h->max_lds = size_t(lds);
+        (void)hipGetLastError();
+    }
     return set_coeffs(h, alpha);
 }
 
@@ -670,7 +692,7 @@ void mg_options_default(mg_options* o) {
     o->levels = 0;
     o->nu_pre = 2;
     o->nu_post = 2;
-    o->coarse_sweeps = 10;
+    o->coarse_sweeps = 20;
     o->max_iters = 100;
     o->omega = 0.8;
     o->semi_threshold = 2.0;

@@ -79,7 +79,10 @@ def test_solve_matches_oracle(sh, prec):
     S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
     L = hierarchy(sh)
     uref, stref = oracle_solution(sh)
-    for tol in (sh.tol, 1e-10):
+    # the forward error is about 300 times the relative residual on the
+    # 70-layer shells (the operator's conditioning), so matching the oracle's
+    # solution to 1e-8 takes a residual near 1e-11
+    for tol in (sh.tol, 1e-11):
         u, st = S.solve(t(b), tol=tol)
         u = n(u)
         rel_res = np.linalg.norm((b - oracle.apply(L[0], u)).ravel()) / np.linalg.norm(b)
@@ -89,7 +92,7 @@ def test_solve_matches_oracle(sh, prec):
         assert st.relres <= tol
         assert rel_res <= tol * 1.01
         assert st.iters <= stref["iters"] + 2
-    # at relative residual 1e-10 the solution matches the oracle to 1e-8
+    # at relative residual 1e-11 the solution matches the oracle to 1e-8
     assert fwd < 1e-8
 
 

@@ -8,8 +8,9 @@ a = (dth/(cos th * dlam))^2 <= threshold; mirror to the north):
 8x4 (dlam = dth = pi/4): rows at -67.5, -22.5 deg have a = 1/cos^2 = 6.83,
 1.17; the equator row could only pair with the polar one, so level 0 merges
 nothing -> 4x4. At dlam = pi/2 the same rows have a = 1.71, 0.29 (both <= 2),
-so the auto rule stops at 4x4; a fixed third level merges both pairs -> 2x2,
-whose single row per hemisphere (centre 45 deg, dth = dlam/2) has a = 0.5.
+so the auto rule stops at 4x4; a third level would merge both pairs, but it
+would have 2 longitudes, below the minimum of 4, so even a fixed count of 3
+levels stops at 4x4.
 
 16x8 (dlam = dth = pi/8): from the equator a = 1.04, 1.45, 3.24, 26.3;
 rows {2,3} merge, rows 1 and 0 stay -> 8x6. At dlam = pi/4: a({2,3}) = 1.17,
@@ -35,12 +36,11 @@ def test_worked_map_8x4():
     sh = _shell(8, 4)
     assert _sizes(build_hierarchy(sh, shellgen.alpha(sh))) == [(8, 4), (4, 4)]
     L = build_hierarchy(sh, shellgen.alpha(sh), levels=3)
-    assert _sizes(L) == [(8, 4), (4, 4), (2, 2)]
+    assert _sizes(L) == [(8, 4), (4, 4)]
     np.testing.assert_allclose(anisotropy(L[0])[:2], [6.83, 1.17], atol=5e-3)
     np.testing.assert_allclose(anisotropy(L[1])[:2], [1.71, 0.29], atol=5e-3)
     assert list(L[1].child_count) == [1, 1, 1, 1]
-    assert list(L[2].child_first) == [0, 2] and list(L[2].child_count) == [2, 2]
-    np.testing.assert_allclose(anisotropy(L[2]), [0.5, 0.5], rtol=1e-12)
+    assert coarsen_rows(anisotropy(L[1]), 2.0) == [(0, 2), (2, 2)]
 
 
 def test_worked_map_16x8():
@@ -67,18 +67,21 @@ def test_threshold_four_reading():
     assert list(L[1].child_count) == [1, 1, 2, 2, 1, 1]
 
 
-@pytest.mark.parametrize("name,sizes", [
-    ("shell64x32x16", [(64, 32), (32, 24), (16, 16), (8, 10), (4, 6)]),
+@pytest.mark.parametrize("name,sizes,stop", [
+    ("shell64x32x16", [(64, 32), (32, 24), (16, 16), (8, 10), (4, 6)], "anisotropy"),
     ("shell384x192x70", [(384, 192), (192, 144), (96, 94), (48, 58), (24, 34),
-                         (12, 20), (6, 12), (3, 8)]),
+                         (12, 20), (6, 12)], "width"),
 ])
-def test_workload_hierarchies(name, sizes):
+def test_workload_hierarchies(name, sizes, stop):
     sh = shellgen.workload(name).with_(nlev=2)
     L = build_hierarchy(sh, shellgen.alpha(sh))
     assert _sizes(L) == sizes
-    assert anisotropy(L[-1]).max() <= 2.0
-    # coarsening stopped for the rule, not for lack of room
     assert anisotropy(L[-2]).max() > 2.0
+    if stop == "anisotropy":
+        assert anisotropy(L[-1]).max() <= 2.0
+    else:
+        # a coarser level would have had fewer than 4 longitudes
+        assert anisotropy(L[-1]).max() > 2.0 and L[-1].nlon // 2 < 4
 
 
 @pytest.mark.parametrize("dims", [(64, 32), (96, 48), (40, 20)])
