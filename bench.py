@@ -46,6 +46,34 @@ def kernel_roofline(stats_list, cls):
             "bytes_per_launch": bytes_per_launch, "GBps": gbps}
 
 
+def file_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(p.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy), or
+    None when no summary covers this workload and kernel class or when the
+    kernel's sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{cls}_{workload}.json")
+    if not os.path.exists(path):
+        return None, "no counter summary for this kernel and workload"
+    with open(path) as f:
+        rec = json.load(f)
+    try:
+        now = file_sha256(rec["sources"])
+    except OSError as e:
+        return None, f"source missing: {e}"
+    if now != rec["sources_sha256"]:
+        return None, "kernel sources changed since the counters were taken"
+    return rec["bytes_per_launch"], rec["kernel"]
+
+
 def cpu_baseline(shell, iters_gpu):
     """The oracle, untuned, on the host: one outer iteration (one V-cycle and
     one FP64 residual) of the same workload, scaled by the GPU's iteration
@@ -83,6 +111,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -100,6 +130,16 @@ def main():
     alpha = torch.from_numpy(shellgen.alpha(sh)).to(dev)
     b = torch.from_numpy(shellgen.rhs(sh)).to(dev)
     torch.cuda.synchronize()
+    if args.copy_probe:
+        # a plain device copy of known size (1 GiB read + 1 GiB written), the
+        # reference that scales hardware byte counters to bytes
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 3 copies of 1 GiB")
 
     t0 = time.perf_counter()
     S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
@@ -150,9 +190,11 @@ def main():
     kern = {c: v for c, v in kern.items() if v}
     dom = max(kern, key=lambda c: kern[c]["avg_ms"] * kern[c]["launches"])
     k = kern[dom]
-    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": k["GBps"],
+    traffic, traffic_note = measured_traffic(sh.name, dom)
+    out["roofline"] = {"bound": "hbm", "kernel_class": dom, "achieved": k["GBps"],
                        "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                       "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                       "frac": k["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
+                       "traffic_source": traffic_note,
                        "avg_launch_ms": k["avg_ms"], "bytes_per_launch": k["bytes_per_launch"],
                        "launches": k["launches"]}
     out["fine_level_kernels"] = {c: {"GBps": v["GBps"], "avg_ms": v["avg_ms"],

@@ -108,12 +108,13 @@ typedef struct {
 /* Kernel classes reported by mg_stats when profiling. */
 enum {
     MG_K_RESIDUAL64 = 0,  /* FP64 update + residual + norm partials (fine)  */
-    MG_K_SMOOTH,          /* block-Jacobi sweep, all levels                  */
+    MG_K_SMOOTH,          /* block-Jacobi sweep from an iterate, all levels  */
     MG_K_RESTRICT,        /* fused residual + restriction                     */
     MG_K_PROLONG,         /* bilinear prolongation (add)                      */
     MG_K_COARSE,          /* coarsest-level solve                             */
     MG_K_ADJOINT,         /* transposed-cycle kernels                         */
     MG_K_OTHER,           /* reductions, copies                               */
+    MG_K_SMOOTH0,         /* first sweep of a level, from zero                */
     MG_NK
 };
 

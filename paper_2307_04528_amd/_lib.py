@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(_HERE, "libmgshell.so")
 MG_MAX_LEVELS = 32
 MG_MAX_NLEV = 128
 MG_HIST = 128
-MG_NK = 7
-KERNEL_CLASSES = ["residual64", "smooth", "restrict", "prolong", "coarse", "adjoint", "other"]
+MG_NK = 8
+KERNEL_CLASSES = ["residual64", "smooth", "restrict", "prolong", "coarse", "adjoint", "other",
+                  "smooth0"]
 
 MG_OK, MG_ERR_NOT_CONVERGED = 0, 1
 MG_ERR_ARG, MG_ERR_HIP, MG_ERR_OOM, MG_ERR_BREAKDOWN = -1, -2, -3, -4

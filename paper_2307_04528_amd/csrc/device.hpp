@@ -154,9 +154,10 @@ void with_nz(int nz, F&& fn) {
     else fn(std::integral_constant<int, 128>{});
 }
 
-// Levels with fewer columns than this cannot fill the GPU with one lane per
-// column; their Thomas sweeps prefetch deeper (latency rather than
-// bandwidth bound).
-constexpr long long kSmallLevelColumns = 1LL << 15;
+// Levels with fewer columns than this run their Thomas sweeps with the
+// deeper prefetch (more layers in flight per lane, fewer lanes): below
+// ~2^19 columns the GPU holds every column at once, so the per-column
+// latency chain, not the bandwidth, sets the time.
+constexpr long long kSmallLevelColumns = 1LL << 19;
 
 }  // namespace mgk

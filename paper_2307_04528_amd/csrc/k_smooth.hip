@@ -18,6 +18,9 @@ namespace mgk {
 #ifndef MG_SMOOTH_WAVES64
 #define MG_SMOOTH_WAVES64 1
 #endif
+#ifndef MG_SMOOTH_KEEP_X
+#define MG_SMOOTH_KEEP_X 0
+#endif
 #ifndef MG_CHUNK32
 #define MG_CHUNK32 4
 #endif
@@ -44,9 +47,9 @@ struct ChunkDepth {
 };
 
 // Thomas solve of one column, z = H_z^{-1} s, with chunked prefetch.
-//   src(kk)               -> s_kk (issues the loads of layer kk)
+//   src(k, kk)            -> s_kk (issues the loads of layer kk)
 //   fwd_sink(k, kk, s)    called once s_k is available (e.g. to store it)
-//   bload(kk, e[NB])      extra per-layer loads needed by the backward sink
+//   bload(k, kk, e[NB])   extra per-layer loads needed by the backward sink
 //   sink(k, kk, z, e[NB]) consumes z_k, top layer first
 // Layers k >= nz (bucket padding) are computed on clamped data and never
 // stored.
@@ -64,7 +67,7 @@ __device__ __forceinline__ void thomas_column(const LevelView<T>& L, int J, uint
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int kk = clampk(c * D + d, nz);
-            bs[buf][d] = src(kk);
+            bs[buf][d] = src(c * D + d, kk);
             bp[buf][d] = ldb<T>(layer(L.invp, kk, Pb), boff);
         }
     };
@@ -92,7 +95,7 @@ __device__ __forceinline__ void thomas_column(const LevelView<T>& L, int J, uint
         for (int d = 0; d < D; ++d) {
             const int kk = clampk(c * D + d, nz);
             if constexpr (!KEEP_P) bq[buf][d] = ldb<T>(layer(L.invp, kk, Pb), boff);
-            if constexpr (NB > 0) bload(kk, be[buf][d]);
+            if constexpr (NB > 0) bload(c * D + d, kk, be[buf][d]);
         }
     };
     T zn = 0;
@@ -123,25 +126,33 @@ __device__ __forceinline__ void sweep_column(const LevelView<T>& L, const T* f, 
     const int nJ = L.nJ, nz = L.nz;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
-    auto src = [&](int kk) -> T {
+    // KEEP_X: the column's own old value is loaded in the forward pass (its
+    // cache lines are those of the east/west neighbours) and kept for the
+    // damping term, instead of being fetched again in the backward pass
+    constexpr bool KX = HAS_X && MG_SMOOTH_KEEP_X != 0;
+    constexpr int NP = ((NZ + D - 1) / D) * D;
+    T xkeep[KX ? NP : 1];
+    auto src = [&](int k, int kk) -> T {
         T s = ldb<T>(layer(f, kk, Pb), b.c);
         if constexpr (HAS_X) {
             gcptr xk = layer(xin, kk, Pb);
             s += tab(L.Tlam, kk * nJ + b.J) * (ldb<T>(xk, b.w) + ldb<T>(xk, b.e)) +
                  tab(L.Tth, kk * (nJ + 1) + b.J) * ldb<T>(xk, b.s) +
                  tab(L.Tth, kk * (nJ + 1) + b.J + 1) * ldb<T>(xk, b.n);
+            if constexpr (KX) xkeep[k] = ldb<T>(xk, b.c);
         }
         return s;
     };
     auto fsink = [&](int, int, T) {};
-    auto bload = [&](int kk, T (&e)[1]) { e[0] = ldb<T>(layer(xin, kk, Pb), b.c); };
+    auto bload = [&](int, int kk, T (&e)[1]) { e[0] = ldb<T>(layer(xin, kk, Pb), b.c); };
     auto sink = [&](int k, int kk, T z, const T (&e)[1]) {
         T out = omega * z;
-        if constexpr (HAS_X) out += keep * e[0];
+        if constexpr (KX) out += keep * xkeep[k];
+        else if constexpr (HAS_X) out += keep * e[0];
         if (k < nz) stb<T>(layer_w(xout, kk, Pb), b.c, out);
     };
-    thomas_column<T, NZ, D, MG_SMOOTH_KEEP_P != 0, HAS_X ? 1 : 0>(L, b.J, b.c, src, fsink,
-                                                                   bload, sink);
+    thomas_column<T, NZ, D, MG_SMOOTH_KEEP_P != 0, (HAS_X && !KX) ? 1 : 0>(
+        L, b.J, b.c, src, fsink, bload, sink);
 }
 
 template <typename T, int NZ, int D, bool HAS_X, bool ROWU>
@@ -297,7 +308,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
     const int nJ = L.nJ, nz = L.nz;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
-    auto src = [&](int kk) -> T {
+    auto src = [&](int, int kk) -> T {
         T s = ldb<T>(layer(xb, kk, Pb), b.c);
         if constexpr (HAS_Z) {
             gcptr zk = layer(zin, kk, Pb);
@@ -313,7 +324,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
             if (k < nz) stb<T>(layer_w(xbout, kk, Pb), b.c, s);
         }
     };
-    auto bload = [&](int kk, T (&e)[1]) { e[0] = ldb<T>(layer(fb, kk, Pb), b.c); };
+    auto bload = [&](int, int kk, T (&e)[1]) { e[0] = ldb<T>(layer(fb, kk, Pb), b.c); };
     auto sink = [&](int k, int kk, T z, const T (&e)[1]) {
         T fo = omega * z;
         if constexpr (ACC) fo += e[0];

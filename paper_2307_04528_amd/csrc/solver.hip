@@ -320,7 +320,7 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
         *result = cur;
         return MG_OK;
     }
-    MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH));
+    MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH0));
     for (int s = 1; s < h->opt.nu_pre; ++s) {
         MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH));
         std::swap(cur, nxt);
@@ -628,7 +628,8 @@ mg_status level_sweep(mg_handle* h, int l, const double* f, const double* xin, d
     Work<T>& w = work<T>(d);
     to_level<T>(h, f, w.f, d.n);
     if (xin) to_level<T>(h, xin, w.xa, d.n);
-    MG_TRY(op_smooth<T>(h, l, w.f, xin ? w.xa : nullptr, w.xb, MG_K_SMOOTH));
+    MG_TRY(op_smooth<T>(h, l, w.f, xin ? w.xa : nullptr, w.xb,
+                        xin ? MG_K_SMOOTH : MG_K_SMOOTH0));
     from_level<T>(h, w.xb, xout, d.n);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return check_launch(h, "level_sweep");
