@@ -189,12 +189,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
 // neighbours from LDS, with the same chunked prefetch as the other column
 // kernels, keeps its new column in the Thomas registers, and after a block
 // barrier overwrites the old iterate; a sweep then costs a few microseconds.
-template <typename T, int NZ>
+// UNIT: block b solves for the b-th unit vector instead of f and writes its
+// result to row b of xout (rows of n values): the grid then computes the
+// solve's explicit matrix, transposed, one row per block.
+template <typename T, int NZ, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* __restrict__ f,
                                                        T* __restrict__ xout, T omega,
                                                        int sweeps) {
     extern __shared__ unsigned char smem_raw[];
     const int plane = int(L.plane), nz = L.nz, nJ = L.nJ, n = plane * nz;
+    if constexpr (UNIT) xout += size_t(blockIdx.x) * size_t(n);
     T* sx = reinterpret_cast<T*>(smem_raw);
     T* sf = sx + n;
     T* sp = sf + n;
@@ -205,7 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     T* str = sth + nz * (nJ + 1);    // [nz+1][nJ]
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         sx[t] = T(0);   // the first sweep starts from zero: same code as the rest
-        sf[t] = f[t];
+        if constexpr (UNIT) sf[t] = (t == int(blockIdx.x)) ? T(1) : T(0);
+        else sf[t] = f[t];
         sp[t] = L.invp[t];
     }
     for (int t = threadIdx.x; t < nz * nJ; t += blockDim.x) stl[t] = L.Tlam[t];
@@ -378,29 +383,36 @@ void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, h
     });
 }
 
+// Launch k_coarse_lds<T, NZ, UNIT> on `blocks` blocks; false if the level
+// does not fit one block's LDS.
+template <typename T, bool UNIT>
+bool launch_coarse_lds(const LevelView<T>& L, const T* f, T* x, T omega, int sweeps,
+                       size_t max_lds, int blocks, hipStream_t s) {
+    const size_t lds = coarse_lds_bytes<T>(L.plane, L.nJ, L.nz);
+    if (L.plane > kBlock || lds > max_lds) return false;
+    int threads = int(((L.plane + 63) / 64) * 64);
+    bool launched = false;
+    with_nz(L.nz, [&](auto nzc) {
+        constexpr int NZ = decltype(nzc)::value;
+        if (lds > 64 * 1024 &&
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_lds<T, NZ, UNIT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(lds)) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        k_coarse_lds<T, NZ, UNIT><<<blocks, threads, lds, s>>>(L, f, x, omega, sweeps);
+        launched = true;
+    });
+    return launched;
+}
+
 template <typename T>
 int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int sweeps,
                  size_t max_lds, hipStream_t s) {
+    if (launch_coarse_lds<T, false>(L, f, xa, omega, sweeps, max_lds, 1, s)) return 0;
     int threads = int(((L.plane + 63) / 64) * 64);
     if (threads > kBlock) threads = kBlock;
-    const size_t lds = (3 * size_t(L.plane) * L.nz + size_t(L.nz) * L.nJ +
-                        size_t(L.nz) * (L.nJ + 1) + size_t(L.nz + 1) * L.nJ) * sizeof(T);
-    if (L.plane <= kBlock && lds <= max_lds) {
-        bool launched = false;
-        with_nz(L.nz, [&](auto nzc) {
-            constexpr int NZ = decltype(nzc)::value;
-            if (lds > 64 * 1024 &&
-                hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_lds<T, NZ>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    int(lds)) != hipSuccess) {
-                (void)hipGetLastError();
-                return;
-            }
-            k_coarse_lds<T, NZ><<<1, threads, lds, s>>>(L, f, xa, omega, sweeps);
-            launched = true;
-        });
-        if (launched) return 0;
-    }
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         k_coarse_solve<T, NZ, MG_CHUNK_SMALL><<<1, threads, 0, s>>>(L, f, xa, xb, omega, sweeps);
@@ -433,6 +445,13 @@ template <typename T>
 void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s) {
     const long long n = L.plane * L.nz;
     k_adjoint_stencil<T><<<blocks_for(n), kBlock, 0, s>>>(L, z, xb, omega, uint32_t(n));
+}
+
+bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int sweeps,
+                  size_t max_lds, hipStream_t s) {
+    const long long n = L.plane * L.nz;
+    if (n > kDenseCoarseMax || n < 1) return false;
+    return launch_coarse_lds<double, true>(L, nullptr, Ct, omega, sweeps, max_lds, int(n), s);
 }
 
 #define MG_INST(T)                                                                          \

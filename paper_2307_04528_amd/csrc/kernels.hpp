@@ -59,6 +59,33 @@ template <typename T>
 int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int sweeps,
                  size_t max_lds, hipStream_t s);
 
+// LDS bytes of the one-block coarsest solve: f, inverse pivots and iterate
+// per cell, plus the three coefficient tables.
+template <typename T>
+inline size_t coarse_lds_bytes(long long plane, int nJ, int nz) {
+    return (3 * size_t(plane) * size_t(nz) + size_t(nz) * nJ + size_t(nz) * (nJ + 1) +
+            size_t(nz + 1) * nJ) * sizeof(T);
+}
+
+// The coarsest-level solve (`sweeps` sweeps from zero) is a linear map
+// x = C f of the level's n cells. coarse_basis writes C^T, row by row (row j
+// is the solve applied to the j-th unit vector), in FP64 into Ct (n*n
+// values), with one block per row and the level held in LDS. Returns false,
+// launching nothing, if n > kDenseCoarseMax or the level does not fit in
+// max_lds bytes of LDS.
+constexpr long long kDenseCoarseMax = 6144;
+bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int sweeps,
+                  size_t max_lds, hipStream_t s);
+
+// B = A^T for n x n row-major matrices (A and B distinct).
+template <typename T>
+void transpose_square(const T* A, T* B, long long n, hipStream_t s);
+
+// x = A f for an n x n row-major matrix: one wavefront per row, partial sums
+// in a fixed order (results are reproducible).
+template <typename T>
+void dense_matvec(const T* A, long long n, const T* f, T* x, hipStream_t s);
+
 // fc = R (f - H x) (sum over children), or R f when x == nullptr.
 template <typename T>
 void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T* f,

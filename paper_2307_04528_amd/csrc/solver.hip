@@ -65,6 +65,19 @@ struct ProfRec {
     hipEvent_t a, b;
 };
 
+// Explicit matrix C of the coarsest-level solve (x = C f), and C^T for the
+// transposed cycle, in both precisions; formed for the current coefficients,
+// omega and number of sweeps.
+struct DenseCoarse {
+    bool enabled = false;   // the coarsest level is small enough
+    bool valid = false;     // matrices match the current coefficients/options
+    long long n = 0;
+    int sweeps = -1;
+    double omega = 0;
+    double *C64 = nullptr, *Ct64 = nullptr;
+    float *C32 = nullptr, *Ct32 = nullptr;
+};
+
 }  // namespace
 
 struct mg_handle {
@@ -81,6 +94,7 @@ struct mg_handle {
     int max_partials = 0;
     size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
     bool have32 = false, have64 = false;
+    DenseCoarse dense;
     std::string err;
     std::vector<ProfRec> recs;
     std::vector<hipEvent_t> events;
@@ -173,6 +187,17 @@ template <>
 Work<float>& work<float>(DevLevel& d) { return d.w32; }
 template <>
 Work<double>& work<double>(DevLevel& d) { return d.w64; }
+
+template <typename T>
+const T* dense_C(const mg_handle* h, bool transposed);
+template <>
+const float* dense_C<float>(const mg_handle* h, bool transposed) {
+    return transposed ? h->dense.Ct32 : h->dense.C32;
+}
+template <>
+const double* dense_C<double>(const mg_handle* h, bool transposed) {
+    return transposed ? h->dense.Ct64 : h->dense.C64;
+}
 
 template <typename T>
 mg_status ensure_work(mg_handle* h) {
@@ -299,6 +324,16 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     T* cur = w.xa;
     T* nxt = w.xb;
     if (l == last) {
+        if (h->dense.valid) {
+            // the coarse solve's explicit matrix: one matrix-vector product
+            {
+                Launch g(h, MG_K_COARSE, l, double(d.n) * (d.n + 2) * sizeof(T));
+                mgk::dense_matvec<T>(dense_C<T>(h, false), d.n, f, cur, h->stream);
+            }
+            MG_TRY(check_launch(h, "dense coarse solve"));
+            *result = cur;
+            return MG_OK;
+        }
         if (d.plane <= mgk::kCoarseSolveColumns) {
             // all coarse sweeps in one single-block launch
             int where = 0;
@@ -375,6 +410,14 @@ mg_status vcycle_T(mg_handle* h, int l) {
     const T om = T(h->opt.omega);
     T* z = nullptr;
     if (l == last) {
+        if (h->dense.valid) {
+            // fbar = C^T xbar
+            {
+                Launch g(h, MG_K_COARSE, l, double(d.n) * (d.n + 2) * sizeof(T));
+                mgk::dense_matvec<T>(dense_C<T>(h, true), d.n, w.xbar, w.fbar, h->stream);
+            }
+            return check_launch(h, "dense transposed coarse solve");
+        }
         // (coarse_sweeps - 1) transposed sweeps, then the transposed first
         // sweep: fbar += omega H_z^{-1} xbar, all as one chain
         return chain_T<T>(h, l, h->opt.coarse_sweeps, true, &z);
@@ -520,6 +563,31 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     return status;
 }
 
+// Form the coarsest solve's matrices for the current pivots, omega and
+// number of sweeps: C^T from the solves of the unit vectors (FP64), C by
+// transposition, FP32 copies of both.
+mg_status rebuild_dense(mg_handle* h) {
+    DenseCoarse& D = h->dense;
+    D.valid = false;
+    if (!D.enabled) return MG_OK;
+    const DevLevel& c = h->lv.back();
+    if (!mgk::coarse_basis(view<double>(c), D.Ct64, h->opt.omega, h->opt.coarse_sweeps,
+                           h->max_lds, h->stream)) {
+        D.enabled = false;   // does not fit: keep the sweeps
+        return MG_OK;
+    }
+    MG_TRY(check_launch(h, "coarse_basis"));
+    mgk::transpose_square<double>(D.Ct64, D.C64, D.n, h->stream);
+    MG_TRY(check_launch(h, "transpose"));
+    mgk::cast<double, float>(D.C64, D.C32, D.n * D.n, h->stream);
+    mgk::cast<double, float>(D.Ct64, D.Ct32, D.n * D.n, h->stream);
+    MG_TRY(check_launch(h, "cast"));
+    D.sweeps = h->opt.coarse_sweeps;
+    D.omega = h->opt.omega;
+    D.valid = true;
+    return MG_OK;
+}
+
 // Device-side coefficients: masses per level, pivots, FP32 copies.
 mg_status set_coeffs(mg_handle* h, const double* alpha) {
     DevLevel& f = h->lv[0];
@@ -540,6 +608,7 @@ mg_status set_coeffs(mg_handle* h, const double* alpha) {
         mgk::pivots(view<double>(d), d.invp64, d.invp32, d.M32, h->stream);
         MG_TRY(check_launch(h, "pivots"));
     }
+    MG_TRY(rebuild_dense(h));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return MG_OK;
 }
@@ -595,6 +664,20 @@ mg_status build(mg_handle* h, const double* alpha) {
                 hipSuccess && lds > 0)
             h->max_lds = size_t(lds);
         (void)hipGetLastError();
+    }
+    {
+        const DevLevel& c = h->lv.back();
+        DenseCoarse& D = h->dense;
+        D.n = c.n;
+        D.enabled = c.n <= mgk::kDenseCoarseMax && c.plane <= mgk::kBlock &&
+                    mgk::coarse_lds_bytes<double>(c.plane, c.nJ, c.nz) <= h->max_lds;
+        if (D.enabled) {
+            const size_t nn = size_t(c.n) * size_t(c.n);
+            MG_TRY(dalloc(h, &D.C64, nn));
+            MG_TRY(dalloc(h, &D.Ct64, nn));
+            MG_TRY(dalloc(h, &D.C32, nn));
+            MG_TRY(dalloc(h, &D.Ct32, nn));
+        }
     }
     return set_coeffs(h, alpha);
 }
@@ -738,8 +821,13 @@ mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
     if (!e.empty()) return fail(h, MG_ERR_ARG, "%s", e.c_str());
     if (opts->levels != h->opt.levels || opts->semi_threshold != h->opt.semi_threshold)
         return fail(h, MG_ERR_ARG, "levels and semi_threshold are fixed at setup");
+    const bool recoarse = opts->coarse_sweeps != h->dense.sweeps || opts->omega != h->dense.omega;
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
+    if (recoarse && h->dense.enabled) {
+        MG_TRY(rebuild_dense(h));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
     return MG_OK;
 }
 

@@ -60,6 +60,65 @@ def test_vcycle_fp32(sh):
     assert rel2(gotT, refT) < 1e-4
 
 
+# The coarsest-level solve takes one of four routes, by the coarsest level's
+# size: its explicit matrix (n <= 6144 cells; every shell above), all sweeps
+# in one block with the level in LDS (<= 256 columns that fit in LDS), all
+# sweeps in one block from global memory (<= 4096 columns), or one launch per
+# sweep. Each case below forces one of the other routes with a fixed level
+# count; the result must be the same V-cycle.
+COARSE_ROUTES = [
+    # coarsest 8x10x128: 10240 cells. FP32 fits in LDS (139 KB), FP64 does
+    # not (278 KB) and runs from global memory
+    (shellgen.Shell("coarse_lds", 64, 32, 128, stretch=1.02), 4),
+    # coarsest 96x72x7: 6912 columns, one launch per sweep
+    (shellgen.Shell("coarse_sweeps", 192, 96, 7, stretch=1.2, thickness=0.05), 2),
+]
+
+
+@pytest.mark.parametrize("case", COARSE_ROUTES, ids=lambda c: c[0].name)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_vcycle_coarse_routes(case, prec):
+    sh, levels = case
+    a = shellgen.alpha(sh)
+    S = solver_for(sh, a, precision=prec, levels=levels, coarse_sweeps=5)
+    L = hierarchy(sh, levels)
+    assert len(L) == levels
+    opt = opts_of(sh, coarse_sweeps=5)
+    f = shellgen.rhs(sh)
+    got = n(S.vcycle(t(f)))
+    ref = oracle.vcycle(L, f, opt)
+    gotT = n(S.vcycle(t(f), transposed=True))
+    refT = oracle.vcycle_T(L, f, opt)
+    err, errT = (rel_inf(got, ref), rel_inf(gotT, refT)) if prec == "fp64" else \
+        (rel2(got, ref), rel2(gotT, refT))
+    log(f"vcycle {sh.name} levels={levels} {prec}: {err:.2e} transposed {errT:.2e}")
+    bar = 1e-12 if prec == "fp64" else 1e-4
+    assert err < bar and errT < bar
+
+
+def test_coarse_matrix_follows_options_and_coefficients():
+    """The explicit coarsest-level matrix is re-formed when the number of
+    coarse sweeps, omega or alpha change."""
+    sh = RAGGED
+    a = shellgen.alpha(sh)
+    S = solver_for(sh, a, precision="fp64")
+    L = hierarchy(sh)
+    f = shellgen.rhs(sh)
+    for nc, om in [(7, 0.8), (7, 0.7), (20, 0.8)]:
+        S.set_options(coarse_sweeps=nc, omega=om)
+        got = n(S.vcycle(t(f)))
+        ref = oracle.vcycle(L, f, opts_of(sh, coarse_sweeps=nc, omega=om))
+        log(f"coarse sweeps {nc} omega {om}: {rel_inf(got, ref):.2e}")
+        assert rel_inf(got, ref) < 1e-12
+    a2 = a * (1.0 + 0.5 * np.random.default_rng(31).random(a.shape))
+    S.update_alpha(t(a2))
+    L2 = oracle.build_hierarchy(sh, a2)
+    got = n(S.vcycle(t(f)))
+    ref = oracle.vcycle(L2, f, opts_of(sh))
+    log(f"new alpha: {rel_inf(got, ref):.2e}")
+    assert rel_inf(got, ref) < 1e-12
+
+
 def test_transposed_vcycle_dot_product_on_gpu():
     sh = DEEP
     S = solver_for(sh, shellgen.alpha(sh), precision="fp64", nu_pre=2, nu_post=1)
