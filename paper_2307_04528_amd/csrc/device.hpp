@@ -72,6 +72,37 @@ __device__ __forceinline__ Nb neighbours(uint32_t col, int nI, int nJ) {
     return b;
 }
 
+// Row-aligned segments: a latitude row of nI columns is cut into
+// wpr = ceil(nI / 64) segments of up to 64 consecutive columns, and one
+// wavefront takes one segment, so the row index is wave-uniform on every
+// level (not only where 64 divides nI). Lanes past the end of the row, and
+// segments past the last row, are marked invalid; their offsets are clamped
+// to a real column so that every load stays in bounds.
+struct Seg {
+    uint32_t c, w, e, s, n;
+    int J;
+    bool valid;
+};
+
+__device__ __forceinline__ Seg segment(int seg, int nI, int nJ, int wpr) {
+    int J = seg / wpr;
+    const int i = (seg - J * wpr) * 64 + int(threadIdx.x & 63u);
+    Seg r;
+    r.valid = J < nJ && i < nI;
+    J = J < nJ ? J : nJ - 1;
+    const int ic = i < nI ? i : nI - 1;
+    const uint32_t col = uint32_t(J) * uint32_t(nI) + uint32_t(ic);
+    r.J = J;
+    r.c = col;
+    r.w = (ic == 0) ? col + uint32_t(nI - 1) : col - 1u;
+    r.e = (ic == nI - 1) ? col - uint32_t(nI - 1) : col + 1u;
+    r.s = (J > 0) ? col - uint32_t(nI) : col;
+    r.n = (J < nJ - 1) ? col + uint32_t(nI) : col;
+    return r;
+}
+
+inline int segments_per_row(int nI) { return (nI + 63) / 64; }
+
 // The same offsets in bytes for element type T (a layer of any per-cell
 // array is < 4 GiB).
 template <typename T>
@@ -79,6 +110,10 @@ struct NbB {
     uint32_t c, w, e, s, n;
     int J;
     __device__ __forceinline__ explicit NbB(const Nb& b)
+        : c(b.c * uint32_t(sizeof(T))), w(b.w * uint32_t(sizeof(T))),
+          e(b.e * uint32_t(sizeof(T))), s(b.s * uint32_t(sizeof(T))),
+          n(b.n * uint32_t(sizeof(T))), J(b.J) {}
+    __device__ __forceinline__ explicit NbB(const Seg& b)
         : c(b.c * uint32_t(sizeof(T))), w(b.w * uint32_t(sizeof(T))),
           e(b.e * uint32_t(sizeof(T))), s(b.s * uint32_t(sizeof(T))),
           n(b.n * uint32_t(sizeof(T))), J(b.J) {}

@@ -123,29 +123,51 @@ __global__ __launch_bounds__(kBlock) void k_fine_mass(LevelView<double> L,
     block_sum_to(bad, partials + blockIdx.x);
 }
 
-// Setup: row-sum form of the Thomas pivots of H_z, per column:
-//   mt_k = M_k + 2 Tlam + Tth(south) + Tth(north)
-//   g_0 = mt_0, g_k = mt_k + Tr_k g_{k-1} / (Tr_k + g_{k-1}),  p_k = Tr_{k+1} + g_k,
-// the textbook pivots D_k - Tr_k^2 / p_{k-1} without the cancellation.
+// Setup: pivots of the twisted (two-sided) factorisation of H_z, per column.
+// The column is eliminated from the bottom up to the layer below m = nz/2 and
+// from the top down to the layer above it; layer m takes both. In row-sum
+// form, with mt_k = M_k + 2 Tlam + Tth(south) + Tth(north) (the row sum of
+// H_z at layer k) and Tr_F the coupling across face F (below layer F):
+//   below m: g_0 = mt_0, g_k = mt_k + Tr_k g_{k-1} / (Tr_k + g_{k-1}),
+//            stored 1 / (Tr_{k+1} + g_k)
+//   above m: h_{nz-1} = mt_{nz-1}, h_k = mt_k + Tr_{k+1} h_{k+1} / (Tr_{k+1} + h_{k+1}),
+//            stored 1 / (Tr_k + h_k)
+//   at m:    stored 1 / (mt_m + Tr_m g_{m-1} / (Tr_m + g_{m-1})
+//                            + Tr_{m+1} h_{m+1} / (Tr_{m+1} + h_{m+1}))
+// These are the textbook pivots D_k - Tr^2 / p of each elimination without
+// the cancellation (every g, h >= mt > 0).
 __global__ __launch_bounds__(kBlock) void k_pivots(LevelView<double> L,
                                                    double* __restrict__ invp64,
                                                    float* __restrict__ invp32,
                                                    float* __restrict__ M32) {
     const uint32_t col = global_index();
     if (col >= uint32_t(L.plane)) return;
-    const int J = int(col / uint32_t(L.nI)), nJ = L.nJ;
+    const int J = int(col / uint32_t(L.nI)), nJ = L.nJ, nz = L.nz, m = nz / 2;
+    auto off = [&](int k) { return size_t(k) * size_t(L.plane) + col; };
+    auto mt = [&](int k) {
+        return L.M[off(k)] + 2.0 * L.Tlam[k * nJ + J] + L.Tth[k * (nJ + 1) + J] +
+               L.Tth[k * (nJ + 1) + J + 1];
+    };
+    auto tr = [&](int F) { return L.Tr[F * nJ + J]; };
+    auto put = [&](int k, double ip) {
+        invp64[off(k)] = ip;
+        invp32[off(k)] = float(ip);
+        M32[off(k)] = float(L.M[off(k)]);
+    };
     double g = 0;
-    for (int k = 0; k < L.nz; ++k) {
-        const size_t o = size_t(k) * L.plane + col;
-        const double mt = L.M[o] + 2.0 * L.Tlam[k * nJ + J] + L.Tth[k * (nJ + 1) + J] +
-                          L.Tth[k * (nJ + 1) + J + 1];
-        const double trb = L.Tr[k * nJ + J];
-        g = (k == 0) ? mt : mt + trb * g / (trb + g);
-        const double ip = 1.0 / (L.Tr[(k + 1) * nJ + J] + g);
-        invp64[o] = ip;
-        invp32[o] = float(ip);
-        M32[o] = float(L.M[o]);
+    for (int k = 0; k < m; ++k) {
+        g = (k == 0) ? mt(0) : mt(k) + tr(k) * g / (tr(k) + g);
+        put(k, 1.0 / (tr(k + 1) + g));
     }
+    double h = 0;
+    for (int k = nz - 1; k > m; --k) {
+        h = (k == nz - 1) ? mt(k) : mt(k) + tr(k + 1) * h / (tr(k + 1) + h);
+        put(k, 1.0 / (tr(k) + h));
+    }
+    double d = mt(m);
+    if (m > 0) d += tr(m) * g / (tr(m) + g);
+    if (m < nz - 1) d += tr(m + 1) * h / (tr(m + 1) + h);
+    put(m, 1.0 / d);
 }
 
 __global__ __launch_bounds__(kBlock) void k_grad_alpha(LevelView<double> L,

@@ -3,32 +3,44 @@
 // One sweep, with the vertical couplings in H_z solved exactly per column:
 //   x_new = (1 - omega) x + omega H_z^{-1} (f + sum_h T_h x_nb)
 // which equals x + omega H_z^{-1}(f - H x) since H = H_z + dH and dH holds
-// only the horizontal off-diagonals -T_h. The column solve is the Thomas
-// algorithm with precomputed inverse pivots (row-sum form, see setup).
+// only the horizontal off-diagonals -T_h.
+//
+// Column solves use the twisted factorisation of H_z (pivots from setup). A
+// pair of wavefronts takes one row-aligned segment of up to 64 columns: the
+// bottom wavefront eliminates the layers below the meeting layer m = nz/2
+// going up, the top wavefront the layers above it going down; after one
+// exchange through LDS both know layer m, and each back-substitutes outward.
+// A wavefront thus walks half a column: the chain of dependent steps is half
+// as long as a one-sided Thomas solve, and everything the back-substitution
+// needs (forward values, couplings, the old iterate) fits in registers, so
+// the second pass reads nothing from memory.
 #include "device.hpp"
 
 namespace mgk {
 
-#ifndef MG_SMOOTH_KEEP_P
-#define MG_SMOOTH_KEEP_P 0
-#endif
 #ifndef MG_SMOOTH_WAVES32
 #define MG_SMOOTH_WAVES32 2
 #endif
 #ifndef MG_SMOOTH_WAVES64
-#define MG_SMOOTH_WAVES64 1
-#endif
-#ifndef MG_SMOOTH_KEEP_X
-#define MG_SMOOTH_KEEP_X 0
+#define MG_SMOOTH_WAVES64 2
 #endif
 #ifndef MG_CHUNK32
-#define MG_CHUNK32 4
+#define MG_CHUNK32 6
 #endif
 #ifndef MG_CHUNK64
 #define MG_CHUNK64 4
 #endif
 #ifndef MG_CHUNK_SMALL
-#define MG_CHUNK_SMALL 8
+#define MG_CHUNK_SMALL 6
+#endif
+#ifndef MG_PAIRS32
+#define MG_PAIRS32 2
+#endif
+#ifndef MG_PAIRS64
+#define MG_PAIRS64 2
+#endif
+#ifndef MG_KEEPX64
+#define MG_KEEPX64 0
 #endif
 
 namespace {
@@ -45,33 +57,57 @@ template <typename T>
 struct ChunkDepth {
     static constexpr int value = std::is_same<T, float>::value ? MG_CHUNK32 : MG_CHUNK64;
 };
+// Wavefront pairs per block of the sweep kernels (the pair's exchange is a
+// block barrier, so fewer pairs per block couple fewer columns).
+template <typename T>
+struct PairsPerBlock {
+    static constexpr int value = std::is_same<T, float>::value ? MG_PAIRS32 : MG_PAIRS64;
+};
 
-// Thomas solve of one column, z = H_z^{-1} s, with chunked prefetch.
-//   src(k, kk)            -> s_kk (issues the loads of layer kk)
-//   fwd_sink(k, kk, s)    called once s_k is available (e.g. to store it)
-//   bload(k, kk, e[NB])   extra per-layer loads needed by the backward sink
-//   sink(k, kk, z, e[NB]) consumes z_k, top layer first
-// Layers k >= nz (bucket padding) are computed on clamped data and never
-// stored.
-template <typename T, int NZ, int D, bool KEEP_P, int NB, class Src, class FSink, class BLoad,
-          class Sink>
-__device__ __forceinline__ void thomas_column(const LevelView<T>& L, int J, uint32_t boff,
-                                              Src src, FSink fwd_sink, BLoad bload, Sink sink) {
-    const int nJ = L.nJ, nz = L.nz;
-    const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
-    constexpr int NC = (NZ + D - 1) / D;
-    T y[NC * D];
-    T ip[KEEP_P ? NC * D : 1];
+// Steps of one wavefront of a pair for the layer bucket NZ.
+template <int NZ>
+constexpr int half_steps() { return (NZ + 1) / 2; }
+template <int NZ, int D>
+constexpr int padded_steps() { return ((half_steps<NZ>() + D - 1) / D) * D; }
+
+// Twisted solve z = H_z^{-1} s of one column by one wavefront of a pair.
+//   top          : false for the bottom wavefront, true for the top (uniform)
+//   xch          : 256 values of LDS private to the pair
+//   src(t, kk)   : issues the loads of layer kk (step t), returns s_kk
+//   inv(kk)      : the stored twisted pivot of layer kk
+//   cpl(F)       : Tr_F, the vertical coupling across face F (below layer F)
+//   fsink(t, kk, s): s of one of this wavefront's layers is available
+//   bload(kk)    : (BL only) a per-layer value the back-substitution needs,
+//                  loaded one chunk ahead like the forward loads
+//   sink(t, kk, z, e): z of one of this wavefront's layers, from the meeting
+//                    layer outward (the top wavefront owns layer m), with
+//                    e = bload(kk) (0 without BL)
+// Step t is layer t (bottom) or nz-1-t (top). Steps beyond a wavefront's
+// layers compute on clamped data and reach neither fsink nor sink. Every
+// thread of the block must call this (one block barrier inside).
+template <typename T, int NZ, int D, bool BL, class Src, class Inv, class Cpl, class FSink,
+          class BLoad, class Sink>
+__device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Src src, Inv inv,
+                                               Cpl cpl, FSink fsink, BLoad bload, Sink sink) {
+    constexpr int NP = padded_steps<NZ, D>();
+    constexpr int NC = NP / D;
+    const int m = nz >> 1, tm = nz - 1 - m;
+    const int nrec = top ? tm : m;   // steps eliminated by this wavefront
+    T y[NP], cb[NP];
     T bs[2][D], bp[2][D];
+    auto lay = [&](int t) {
+        const int k = top ? nz - 1 - t : t;
+        return k < 0 ? 0 : (k < nz ? k : nz - 1);
+    };
     auto load = [&](int c, int buf) {
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const int kk = clampk(c * D + d, nz);
-            bs[buf][d] = src(c * D + d, kk);
-            bp[buf][d] = ldb<T>(layer(L.invp, kk, Pb), boff);
+            const int t = c * D + d, kk = lay(t);
+            bs[buf][d] = src(t, kk);
+            bp[buf][d] = inv(kk);
         }
     };
-    T yp = 0;
+    T vp = 0, sm = 0, im = 0;
     load(0, 0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -79,116 +115,161 @@ __device__ __forceinline__ void thomas_column(const LevelView<T>& L, int J, uint
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            const int k = c * D + d;
-            const int kk = clampk(k, nz);
-            fwd_sink(k, kk, bs[c & 1][d]);
-            yp = (bs[c & 1][d] + tab(L.Tr, kk * nJ + J) * yp) * bp[c & 1][d];
-            y[k] = yp;
-            if constexpr (KEEP_P) ip[k] = bp[c & 1][d];
+            const int t = c * D + d, kk = lay(t);
+            const T s = bs[c & 1][d], ip = bp[c & 1][d];
+            if (t < nrec || (top && t == tm)) fsink(t, kk, s);
+            // couplings to the layer eliminated before this one and to the
+            // one after it
+            const T cf = cpl(top ? kk + 1 : kk), cn = cpl(top ? kk : kk + 1);
+            const T v = (s + cf * vp) * ip;
+            y[t] = v;
+            cb[t] = cn * ip;
+            if (t == tm) {
+                sm = s;
+                im = ip;
+            }
+            vp = (t < nrec) ? v : vp;
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    T bq[2][D];
-    T be[2][D][NB > 0 ? NB : 1];
+    T be[2][BL ? D : 1];
     auto load_back = [&](int c, int buf) {
+        if constexpr (BL) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const int kk = clampk(c * D + d, nz);
-            if constexpr (!KEEP_P) bq[buf][d] = ldb<T>(layer(L.invp, kk, Pb), boff);
-            if constexpr (NB > 0) bload(c * D + d, kk, be[buf][d]);
+            for (int d = 0; d < D; ++d) be[buf][d] = bload(lay(c * D + d));
         }
     };
-    T zn = 0;
     load_back(NC - 1, (NC - 1) & 1);
+    // meeting layer: x_m = (s_m + Tr_m y_{m-1} + Tr_{m+1} z_{m+1}) / d_m
+    const int lane = int(threadIdx.x & 63u);
+    if (!top) {
+        xch[lane] = vp;
+    } else {
+        xch[64 + lane] = vp;
+        xch[128 + lane] = sm;
+        xch[192 + lane] = im;
+    }
+    __syncthreads();
+    const T xm =
+        (xch[128 + lane] + cpl(m) * xch[lane] + cpl(m + 1) * xch[64 + lane]) * xch[192 + lane];
+    T xv = xm;
 #pragma unroll
     for (int c = NC - 1; c >= 0; --c) {
-        if (c > 0) load_back(c - 1, (c - 1) & 1);
-        __builtin_amdgcn_sched_barrier(0);
+        if (BL && c > 0) load_back(c - 1, (c - 1) & 1);
+        if constexpr (BL) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int d = D - 1; d >= 0; --d) {
-            const int k = c * D + d;
-            const int kk = clampk(k, nz);
-            T p;
-            if constexpr (KEEP_P) p = ip[k]; else p = bq[c & 1][d];
-            zn = (k < nz) ? y[k] + tab(L.Tr, (kk + 1) * nJ + J) * p * zn : T(0);
-            sink(k, kk, zn, be[c & 1][d]);
+            const int t = c * D + d, kk = lay(t);
+            const T e = BL ? be[c & 1][BL ? d : 0] : T(0);
+            if (top && t == tm) {
+                sink(t, kk, xm, e);
+            } else if (t < nrec) {
+                xv = y[t] + cb[t] * xv;
+                sink(t, kk, xv, e);
+            }
         }
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (BL) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// One forward sweep of one column (see the file comment); xin == nullptr
-// (HAS_X false): the sweep from zero, omega H_z^{-1} f.
-template <typename T, int NZ, int D, bool HAS_X, bool ROWU>
-__device__ __forceinline__ void sweep_column(const LevelView<T>& L, const T* f, const T* xin,
-                                             T* xout, T omega, uint32_t col) {
-    const NbB<T> b(neighbours<ROWU>(col, L.nI, L.nJ));
-    const int nJ = L.nJ, nz = L.nz;
+// Keep the old iterate of a column in registers between the two passes
+// (FP32), or load it again in the back-substitution (FP64, where keeping it
+// would cost the second wavefront per SIMD).
+template <typename T>
+struct KeepX {
+    static constexpr bool value = std::is_same<T, float>::value ? true : (MG_KEEPX64 != 0);
+};
+
+// One sweep of the segment's columns (see the file comment); HAS_X false:
+// the sweep from zero, omega H_z^{-1} f.
+template <typename T, int NZ, int D, bool HAS_X>
+__device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f, const T* xin,
+                                              T* xout, T omega, const Seg& g, bool top,
+                                              T* xch) {
+    const NbB<T> b(g);
+    const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
-    // KEEP_X: the column's own old value is loaded in the forward pass (its
-    // cache lines are those of the east/west neighbours) and kept for the
-    // damping term, instead of being fetched again in the backward pass
-    constexpr bool KX = HAS_X && MG_SMOOTH_KEEP_X != 0;
-    constexpr int NP = ((NZ + D - 1) / D) * D;
-    T xkeep[KX ? NP : 1];
-    auto src = [&](int k, int kk) -> T {
+    constexpr bool KX = HAS_X && KeepX<T>::value;
+    T xk[KX ? padded_steps<NZ, D>() : 1];
+    auto src = [&](int t, int kk) -> T {
         T s = ldb<T>(layer(f, kk, Pb), b.c);
         if constexpr (HAS_X) {
-            gcptr xk = layer(xin, kk, Pb);
-            s += tab(L.Tlam, kk * nJ + b.J) * (ldb<T>(xk, b.w) + ldb<T>(xk, b.e)) +
-                 tab(L.Tth, kk * (nJ + 1) + b.J) * ldb<T>(xk, b.s) +
-                 tab(L.Tth, kk * (nJ + 1) + b.J + 1) * ldb<T>(xk, b.n);
-            if constexpr (KX) xkeep[k] = ldb<T>(xk, b.c);
+            gcptr xl = layer(xin, kk, Pb);
+            s += tab(L.Tlam, kk * nJ + J) * (ldb<T>(xl, b.w) + ldb<T>(xl, b.e)) +
+                 tab(L.Tth, kk * (nJ + 1) + J) * ldb<T>(xl, b.s) +
+                 tab(L.Tth, kk * (nJ + 1) + J + 1) * ldb<T>(xl, b.n);
+            if constexpr (KX) xk[t] = ldb<T>(xl, b.c);
         }
         return s;
     };
-    auto fsink = [&](int, int, T) {};
-    auto bload = [&](int, int kk, T (&e)[1]) { e[0] = ldb<T>(layer(xin, kk, Pb), b.c); };
-    auto sink = [&](int k, int kk, T z, const T (&e)[1]) {
+    auto inv = [&](int kk) -> T { return ldb<T>(layer(L.invp, kk, Pb), b.c); };
+    auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
+    auto fsink = [](int, int, T) {};
+    auto bload = [&](int kk) -> T { return ldb<T>(layer(xin, kk, Pb), b.c); };
+    auto sink = [&](int t, int kk, T z, T e) {
         T out = omega * z;
-        if constexpr (KX) out += keep * xkeep[k];
-        else if constexpr (HAS_X) out += keep * e[0];
-        if (k < nz) stb<T>(layer_w(xout, kk, Pb), b.c, out);
+        if constexpr (KX) out += keep * xk[t];
+        else if constexpr (HAS_X) out += keep * e;
+        if (g.valid) stb<T>(layer_w(xout, kk, Pb), b.c, out);
     };
-    thomas_column<T, NZ, D, MG_SMOOTH_KEEP_P != 0, (HAS_X && !KX) ? 1 : 0>(
-        L, b.J, b.c, src, fsink, bload, sink);
+    twisted_column<T, NZ, D, HAS_X && !KX>(L.nz, top, xch, src, inv, cpl, fsink, bload, sink);
 }
 
-template <typename T, int NZ, int D, bool HAS_X, bool ROWU>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
+// Wavefront w of a block: pair w/2 of the block, bottom (even w) or top.
+struct PairOf {
+    int pair;
+    bool top;
+};
+__device__ __forceinline__ PairOf pair_of_wave() {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    return {wave >> 1, (wave & 1) != 0};
+}
+
+template <typename T, int NZ, int D, bool HAS_X>
+__global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
+__attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
 void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
-              T* __restrict__ xout, T omega) {
-    const uint32_t col = global_index();
-    if (col >= uint32_t(L.plane)) return;
-    sweep_column<T, NZ, D, HAS_X, ROWU>(L, f, xin, xout, omega, col);
+              T* __restrict__ xout, T omega, int wpr) {
+    constexpr int PB = PairsPerBlock<T>::value;
+    __shared__ T xch[PB][256];
+    const PairOf p = pair_of_wave();
+    const Seg g = segment(int(logical_block()) * PB + p.pair, L.nI, L.nJ, wpr);
+    sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
 }
 
-// The coarsest level in one launch: one block does every sweep from zero,
-// ping-ponging between xa and xb, with a block barrier between sweeps (the
-// global writes of a sweep are visible to the whole block after it). The
-// result is in xa if sweeps is odd, else in xb.
+// The coarsest level in one launch from global memory: one block does every
+// sweep from zero, segment by segment, ping-ponging between xa and xb, with
+// a block barrier between sweeps (the global writes of a sweep are visible
+// to the whole block after it). The result is in xa if sweeps is odd, else
+// in xb.
 template <typename T, int NZ, int D>
 __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T* __restrict__ f,
-                                                       T* xa, T* xb, T omega, int sweeps) {
-    const uint32_t plane = uint32_t(L.plane);
+                                                       T* xa, T* xb, T omega, int sweeps,
+                                                       int wpr) {
+    __shared__ T xch[kBlock / 128][256];
+    const PairOf p = pair_of_wave();
+    const int nseg = L.nJ * wpr;
     for (int s = 0; s < sweeps; ++s) {
         T* xout = (s & 1) ? xb : xa;
         const T* xin = (s & 1) ? xa : xb;
-        for (uint32_t col = threadIdx.x; col < plane; col += blockDim.x) {
-            if (s == 0) sweep_column<T, NZ, D, false, false>(L, f, nullptr, xout, omega, col);
-            else sweep_column<T, NZ, D, true, false>(L, f, xin, xout, omega, col);
+        for (int s0 = 0; s0 < nseg; s0 += kBlock / 128) {
+            const Seg g = segment(s0 + p.pair, L.nI, L.nJ, wpr);
+            if (s == 0)
+                sweep_segment<T, NZ, D, false>(L, f, nullptr, xout, omega, g, p.top, xch[p.pair]);
+            else
+                sweep_segment<T, NZ, D, true>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
-// The coarsest level in one launch with its data in LDS: one lane per column
-// (plane <= blockDim); the right-hand side, the inverse pivots and the
-// iterate are staged in LDS ([k][col]) once. A sweep reads the old
-// neighbours from LDS, with the same chunked prefetch as the other column
-// kernels, keeps its new column in the Thomas registers, and after a block
-// barrier overwrites the old iterate; a sweep then costs a few microseconds.
+// The coarsest level in one launch with its data in LDS: a pair of
+// wavefronts per 64 columns (plane <= kCoarseLdsColumns); the right-hand
+// side, the pivots, the iterate and the coefficient tables are staged in
+// LDS ([k][col]) once. A sweep reads the old neighbours from LDS, keeps its
+// new half-column in registers, and after a block barrier overwrites the old
+// iterate; a sweep then costs a few microseconds.
 // UNIT: block b solves for the b-th unit vector instead of f and writes its
 // result to row b of xout (rows of n values): the grid then computes the
 // solve's explicit matrix, transposed, one row per block.
@@ -202,11 +283,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     T* sx = reinterpret_cast<T*>(smem_raw);
     T* sf = sx + n;
     T* sp = sf + n;
-    // the coefficient tables too (read from LDS inside the sweep loop, they
-    // are not hoisted out of it into registers)
     T* stl = sp + n;                 // [nz][nJ]
     T* sth = stl + nz * nJ;          // [nz][nJ+1]
     T* str = sth + nz * (nJ + 1);    // [nz+1][nJ]
+    T* xch = str + (nz + 1) * nJ;    // 256 per pair
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         sx[t] = T(0);   // the first sweep starts from zero: same code as the rest
         if constexpr (UNIT) sf[t] = (t == int(blockIdx.x)) ? T(1) : T(0);
@@ -217,84 +297,50 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     for (int t = threadIdx.x; t < nz * (nJ + 1); t += blockDim.x) sth[t] = L.Tth[t];
     for (int t = threadIdx.x; t < (nz + 1) * nJ; t += blockDim.x) str[t] = L.Tr[t];
     __syncthreads();
-    const int col = threadIdx.x;
+    const PairOf p = pair_of_wave();
+    const int col = p.pair * 64 + int(threadIdx.x & 63u);
     const bool active = col < plane;
     const Nb b = neighbours<false>(active ? uint32_t(col) : 0u, L.nI, nJ);
     constexpr int D = MG_CHUNK_SMALL;
-    constexpr int NC = (NZ + D - 1) / D;
+    constexpr int NP = padded_steps<NZ, D>();
     const T keep = T(1) - omega;
-    T y[NC * D];
+    const int m = nz >> 1, nown = p.top ? nz - m : m;   // layers this wavefront writes
+    T xk[NP];
+    auto lay = [&](int t) {
+        const int k = p.top ? nz - 1 - t : t;
+        return k < 0 ? 0 : (k < nz ? k : nz - 1);
+    };
     for (int s = 0; s < sweeps; ++s) {
         // opaque copies of the strides: the per-layer LDS addresses are then
         // recomputed each sweep instead of being hoisted out of the sweep
         // loop into hundreds of registers (the empty asm emits nothing)
         int pl = plane, nj = nJ;
         asm volatile("" : "+s"(pl), "+s"(nj));
-        if (active) {
-            T bs[2][D], bp[2][D];
-            auto load = [&](int c, int buf) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int kk = clampk(c * D + d, nz);
-                    const T* xk = sx + kk * pl;
-                    bs[buf][d] = sf[kk * pl + b.c] +
-                                 stl[kk * nj + b.J] * (xk[b.w] + xk[b.e]) +
-                                 sth[kk * (nj + 1) + b.J] * xk[b.s] +
-                                 sth[kk * (nj + 1) + b.J + 1] * xk[b.n];
-                    bp[buf][d] = sp[kk * pl + b.c];
-                }
-            };
-            T yp = 0;
-            load(0, 0);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                if (c + 1 < NC) load(c + 1, (c + 1) & 1);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int kk = clampk(c * D + d, nz);
-                    yp = (bs[c & 1][d] + str[kk * nj + b.J] * yp) * bp[c & 1][d];
-                    y[c * D + d] = yp;
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            T bx[2][D], bq[2][D], bt[2][D];
-            auto load_back = [&](int c, int buf) {
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int kk = clampk(c * D + d, nz);
-                    bx[buf][d] = sx[kk * pl + b.c];
-                    bq[buf][d] = sp[kk * pl + b.c];
-                    bt[buf][d] = str[(kk + 1) * nj + b.J];
-                }
-            };
-            T zn = 0;
-            load_back(NC - 1, (NC - 1) & 1);
-#pragma unroll
-            for (int c = NC - 1; c >= 0; --c) {
-                if (c > 0) load_back(c - 1, (c - 1) & 1);
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int d = D - 1; d >= 0; --d) {
-                    const int k = c * D + d;
-                    zn = (k < nz) ? y[k] + bt[c & 1][d] * bq[c & 1][d] * zn : T(0);
-                    y[k] = omega * zn + keep * bx[c & 1][d];   // the new iterate
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
+        auto src = [&](int t, int kk) -> T {
+            const T* xl = sx + kk * pl;
+            xk[t] = xl[b.c];
+            return sf[kk * pl + b.c] + stl[kk * nj + b.J] * (xl[b.w] + xl[b.e]) +
+                   sth[kk * (nj + 1) + b.J] * xl[b.s] + sth[kk * (nj + 1) + b.J + 1] * xl[b.n];
+        };
+        auto inv = [&](int kk) -> T { return sp[kk * pl + b.c]; };
+        auto cpl = [&](int F) -> T { return str[F * nj + b.J]; };
+        auto fsink = [](int, int, T) {};
+        auto bload = [](int) -> T { return T(0); };
+        auto sink = [&](int t, int, T z, T) { xk[t] = omega * z + keep * xk[t]; };
+        twisted_column<T, NZ, D, false>(nz, p.top, xch + p.pair * 256, src, inv, cpl, fsink,
+                                        bload, sink);
         __syncthreads();   // every lane has read the old iterate
         if (active) {
 #pragma unroll
-            for (int k = 0; k < NZ; ++k)
-                if (k < nz) sx[k * plane + b.c] = y[k];
+            for (int t = 0; t < NP; ++t)
+                if (t < nown) sx[lay(t) * plane + b.c] = xk[t];
         }
         __syncthreads();   // the new iterate is complete
     }
     if (active) {
 #pragma unroll
-        for (int k = 0; k < NZ; ++k)
-            if (k < nz) xout[size_t(k) * plane + b.c] = y[k];
+        for (int t = 0; t < NP; ++t)
+            if (t < nown) xout[size_t(lay(t)) * plane + b.c] = xk[t];
     }
 }
 
@@ -302,44 +348,48 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
 // Transposed sweep chain kernel:
 //   xb' = HAS_Z ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout)
 //   z = H_z^{-1} xb';  fb = (ACC ? fb : 0) + omega z;  zout = z (if set)
-template <typename T, int NZ, int D, bool HAS_Z, bool ACC, bool ROWU>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
+template <typename T, int NZ, int D, bool HAS_Z, bool ACC>
+__global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
+__attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
 void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
                 T* xbout,  // may alias xb
-                T* __restrict__ zout, T* __restrict__ fb, T omega) {
-    const uint32_t col = global_index();
-    if (col >= uint32_t(L.plane)) return;
-    const NbB<T> b(neighbours<ROWU>(col, L.nI, L.nJ));
-    const int nJ = L.nJ, nz = L.nz;
+                T* __restrict__ zout, T* __restrict__ fb, T omega, int wpr) {
+    constexpr int PB = PairsPerBlock<T>::value;
+    __shared__ T xch[PB][256];
+    const PairOf p = pair_of_wave();
+    const Seg g = segment(int(logical_block()) * PB + p.pair, L.nI, L.nJ, wpr);
+    const NbB<T> b(g);
+    const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
     auto src = [&](int, int kk) -> T {
         T s = ldb<T>(layer(xb, kk, Pb), b.c);
         if constexpr (HAS_Z) {
             gcptr zk = layer(zin, kk, Pb);
-            const T h = tab(L.Tlam, kk * nJ + b.J) * (ldb<T>(zk, b.w) + ldb<T>(zk, b.e)) +
-                        tab(L.Tth, kk * (nJ + 1) + b.J) * ldb<T>(zk, b.s) +
-                        tab(L.Tth, kk * (nJ + 1) + b.J + 1) * ldb<T>(zk, b.n);
+            const T h = tab(L.Tlam, kk * nJ + J) * (ldb<T>(zk, b.w) + ldb<T>(zk, b.e)) +
+                        tab(L.Tth, kk * (nJ + 1) + J) * ldb<T>(zk, b.s) +
+                        tab(L.Tth, kk * (nJ + 1) + J + 1) * ldb<T>(zk, b.n);
             s = keep * s + omega * h;
         }
         return s;
     };
-    auto fsink = [&](int k, int kk, T s) {
+    auto inv = [&](int kk) -> T { return ldb<T>(layer(L.invp, kk, Pb), b.c); };
+    auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
+    auto fsink = [&](int, int kk, T s) {
         if constexpr (HAS_Z) {
-            if (k < nz) stb<T>(layer_w(xbout, kk, Pb), b.c, s);
+            if (g.valid) stb<T>(layer_w(xbout, kk, Pb), b.c, s);
         }
     };
-    auto bload = [&](int, int kk, T (&e)[1]) { e[0] = ldb<T>(layer(fb, kk, Pb), b.c); };
-    auto sink = [&](int k, int kk, T z, const T (&e)[1]) {
+    auto bload = [&](int kk) -> T { return ldb<T>(layer(fb, kk, Pb), b.c); };
+    auto sink = [&](int, int kk, T z, T e) {
         T fo = omega * z;
-        if constexpr (ACC) fo += e[0];
-        if (k < nz) {
+        if constexpr (ACC) fo += e;
+        if (g.valid) {
             if (zout) stb<T>(layer_w(zout, kk, Pb), b.c, z);
             stb<T>(layer_w(fb, kk, Pb), b.c, fo);
         }
     };
-    thomas_column<T, NZ, ChunkDepth<T>::value, false, ACC ? 1 : 0>(L, b.J, b.c, src, fsink,
-                                                                    bload, sink);
+    twisted_column<T, NZ, D, ACC>(L.nz, p.top, xch[p.pair], src, inv, cpl, fsink, bload, sink);
 }
 
 // xb = (1-omega) xb + omega sum_h T_h z_nb, one lane per cell.
@@ -360,24 +410,31 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_stencil(LevelView<T> L,
     xb[t] = (T(1) - omega) * xb[t] + omega * h;
 }
 
+// Blocks of PB wavefront pairs covering every segment.
+template <typename T>
+inline int pair_blocks(const int nJ, const int wpr) {
+    const long long nseg = (long long)nJ * wpr;
+    constexpr int per = PairsPerBlock<T>::value;
+    return int((nseg + per - 1) / per);
+}
+
 }  // namespace
 
 template <typename T>
 void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, hipStream_t s) {
-    const int nb = blocks_for(L.plane);
+    const int wpr = segments_per_row(L.nI);
+    const int nb = pair_blocks<T>(L.nJ, wpr);
+    constexpr int threads = 128 * PairsPerBlock<T>::value;
     const bool small = L.plane < kSmallLevelColumns;
-    const bool rowu = L.nI % 64 == 0;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int DB = ChunkDepth<T>::value, DS = MG_CHUNK_SMALL;
-#define MG_SMOOTH_LAUNCH(D, HX, RU) \
-    k_smooth<T, NZ, D, HX, RU><<<nb, kBlock, 0, s>>>(L, f, xin, xout, omega)
+#define MG_SMOOTH_LAUNCH(D, HX) \
+    k_smooth<T, NZ, D, HX><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr)
         if (small) {
-            if (xin) { if (rowu) MG_SMOOTH_LAUNCH(DS, true, true); else MG_SMOOTH_LAUNCH(DS, true, false); }
-            else { if (rowu) MG_SMOOTH_LAUNCH(DS, false, true); else MG_SMOOTH_LAUNCH(DS, false, false); }
+            if (xin) MG_SMOOTH_LAUNCH(DS, true); else MG_SMOOTH_LAUNCH(DS, false);
         } else {
-            if (xin) { if (rowu) MG_SMOOTH_LAUNCH(DB, true, true); else MG_SMOOTH_LAUNCH(DB, true, false); }
-            else { if (rowu) MG_SMOOTH_LAUNCH(DB, false, true); else MG_SMOOTH_LAUNCH(DB, false, false); }
+            if (xin) MG_SMOOTH_LAUNCH(DB, true); else MG_SMOOTH_LAUNCH(DB, false);
         }
 #undef MG_SMOOTH_LAUNCH
     });
@@ -389,8 +446,8 @@ template <typename T, bool UNIT>
 bool launch_coarse_lds(const LevelView<T>& L, const T* f, T* x, T omega, int sweeps,
                        size_t max_lds, int blocks, hipStream_t s) {
     const size_t lds = coarse_lds_bytes<T>(L.plane, L.nJ, L.nz);
-    if (L.plane > kBlock || lds > max_lds) return false;
-    int threads = int(((L.plane + 63) / 64) * 64);
+    if (L.plane > kCoarseLdsColumns || lds > max_lds) return false;
+    const int threads = int((L.plane + 63) / 64) * 128;
     bool launched = false;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
@@ -411,11 +468,11 @@ template <typename T>
 int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int sweeps,
                  size_t max_lds, hipStream_t s) {
     if (launch_coarse_lds<T, false>(L, f, xa, omega, sweeps, max_lds, 1, s)) return 0;
-    int threads = int(((L.plane + 63) / 64) * 64);
-    if (threads > kBlock) threads = kBlock;
+    const int wpr = segments_per_row(L.nI);
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
-        k_coarse_solve<T, NZ, MG_CHUNK_SMALL><<<1, threads, 0, s>>>(L, f, xa, xb, omega, sweeps);
+        k_coarse_solve<T, NZ, MG_CHUNK_SMALL><<<1, kBlock, 0, s>>>(L, f, xa, xb, omega, sweeps,
+                                                                   wpr);
     });
     return (sweeps & 1) ? 0 : 1;
 }
@@ -423,19 +480,18 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
 template <typename T>
 void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
                       T* fb, T omega, bool accumulate, hipStream_t s) {
-    const int nb = blocks_for(L.plane);
-    const bool rowu = L.nI % 64 == 0;
+    const int wpr = segments_per_row(L.nI);
+    const int nb = pair_blocks<T>(L.nJ, wpr);
+    constexpr int threads = 128 * PairsPerBlock<T>::value;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int D = ChunkDepth<T>::value;
-#define MG_SMOOTHT_LAUNCH(HZ, AC, RU) \
-    k_smooth_T<T, NZ, D, HZ, AC, RU><<<nb, kBlock, 0, s>>>(L, xb, zin, xbout, zout, fb, omega)
+#define MG_SMOOTHT_LAUNCH(HZ, AC) \
+    k_smooth_T<T, NZ, D, HZ, AC><<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega, wpr)
         if (zin) {
-            if (accumulate) { if (rowu) MG_SMOOTHT_LAUNCH(true, true, true); else MG_SMOOTHT_LAUNCH(true, true, false); }
-            else { if (rowu) MG_SMOOTHT_LAUNCH(true, false, true); else MG_SMOOTHT_LAUNCH(true, false, false); }
+            if (accumulate) MG_SMOOTHT_LAUNCH(true, true); else MG_SMOOTHT_LAUNCH(true, false);
         } else {
-            if (accumulate) { if (rowu) MG_SMOOTHT_LAUNCH(false, true, true); else MG_SMOOTHT_LAUNCH(false, true, false); }
-            else { if (rowu) MG_SMOOTHT_LAUNCH(false, false, true); else MG_SMOOTHT_LAUNCH(false, false, false); }
+            if (accumulate) MG_SMOOTHT_LAUNCH(false, true); else MG_SMOOTHT_LAUNCH(false, false);
         }
 #undef MG_SMOOTHT_LAUNCH
     });

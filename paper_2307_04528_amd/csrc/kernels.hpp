@@ -16,7 +16,7 @@ struct LevelView {
     const T* Tth;    // [nz][nJ+1], face F south of row F
     const T* Tr;     // [nz+1][nJ], face F below layer F
     const T* M;      // [nz][plane] mass sum(alpha V)
-    const T* invp;   // [nz][plane] inverse Thomas pivots of H_z
+    const T* invp;   // [nz][plane] inverse pivots of the twisted factorisation of H_z
 };
 
 // Maps between a fine level and the next coarser one.
@@ -52,19 +52,21 @@ void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
 // The whole coarsest-level solve in one launch (one block): `sweeps` sweeps
 // from zero, ping-ponging between xa and xb. Returns 0 if the result is in
 // xa, 1 if in xb. Meant for levels of at most kCoarseSolveColumns columns;
-// levels of at most kBlock columns whose data fit in max_lds bytes of LDS
-// (three per-cell arrays) run entirely in LDS.
+// levels of at most kCoarseLdsColumns columns whose data fit in max_lds bytes
+// of LDS (see coarse_lds_bytes) run entirely in LDS.
 constexpr long long kCoarseSolveColumns = 4096;
+constexpr long long kCoarseLdsColumns = 128;
 template <typename T>
 int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int sweeps,
                  size_t max_lds, hipStream_t s);
 
-// LDS bytes of the one-block coarsest solve: f, inverse pivots and iterate
-// per cell, plus the three coefficient tables.
+// LDS bytes of the one-block coarsest solve: f, pivots and iterate per cell,
+// the three coefficient tables, and the exchange slots of two wavefront
+// pairs.
 template <typename T>
 inline size_t coarse_lds_bytes(long long plane, int nJ, int nz) {
     return (3 * size_t(plane) * size_t(nz) + size_t(nz) * nJ + size_t(nz) * (nJ + 1) +
-            size_t(nz + 1) * nJ) * sizeof(T);
+            size_t(nz + 1) * nJ + 512) * sizeof(T);
 }
 
 // The coarsest-level solve (`sweeps` sweeps from zero) is a linear map
@@ -135,8 +137,9 @@ void sum_partials(const double* partials, int n, double* out, hipStream_t s);
 // are not finite and > 0 (as FP64 partials).
 int fine_mass(const LevelView<double>& L, const double* V, const double* alpha,
               double* M, double* partials, hipStream_t s);
-// Setup: row-sum Thomas pivots of H_z; inverse pivots in FP64 and FP32 and
-// an FP32 copy of M.
+// Setup: row-sum pivots of the twisted factorisation of H_z (eliminated from
+// both ends toward layer nz/2); inverse pivots in FP64 and FP32 and an FP32
+// copy of M.
 void pivots(const LevelView<double>& L, double* invp64, float* invp32, float* M32,
             hipStream_t s);
 

@@ -669,7 +669,7 @@ mg_status build(mg_handle* h, const double* alpha) {
         const DevLevel& c = h->lv.back();
         DenseCoarse& D = h->dense;
         D.n = c.n;
-        D.enabled = c.n <= mgk::kDenseCoarseMax && c.plane <= mgk::kBlock &&
+        D.enabled = c.n <= mgk::kDenseCoarseMax && c.plane <= mgk::kCoarseLdsColumns &&
                     mgk::coarse_lds_bytes<double>(c.plane, c.nJ, c.nz) <= h->max_lds;
         if (D.enabled) {
             const size_t nn = size_t(c.n) * size_t(c.n);
