@@ -103,6 +103,17 @@ __device__ __forceinline__ Seg segment(int seg, int nI, int nJ, int wpr) {
 
 inline int segments_per_row(int nI) { return (nI + 63) / 64; }
 
+// Row-tiled segments: the R wavefronts (or wavefront pairs) r = 0..R-1 of
+// block b take the same 64-column range of R consecutive rows, so most of
+// the latitude neighbours a stencil reads belong to the same block and are
+// read at about the same time (from the CU's cache), not by a block that
+// runs much earlier or later. Rows past nJ are invalid segments.
+__device__ __forceinline__ Seg tiled_segment(int b, int r, int R, int nI, int nJ, int wpr) {
+    const int band = b / wpr, s = b - band * wpr;
+    return segment((band * R + r) * wpr + s, nI, nJ, wpr);
+}
+inline int tiled_blocks(int nJ, int wpr, int R) { return ((nJ + R - 1) / R) * wpr; }
+
 // The same offsets in bytes for element type T (a layer of any per-cell
 // array is < 4 GiB).
 template <typename T>

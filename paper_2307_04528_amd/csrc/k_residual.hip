@@ -33,18 +33,20 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __res
     y[t] = HAS_F ? f[t] - h : h;
 }
 
-// FP64 refinement step on the finest level, one lane per column:
+// FP64 refinement step on the finest level, one lane per column (row-tiled
+// segments, one wavefront per row of the block's tile):
 //   unew = uin + e (HAS_E; written to uout), r = b - H unew (stored as TR),
 //   per-block partial sums of r^2 in FP64.
-template <typename TE, typename TR, int NZ, bool HAS_E, bool ROWU>
+template <typename TE, typename TR, int NZ, bool HAS_E>
 __global__ __launch_bounds__(kBlock) void k_residual_update(
     LevelView<double> L, const double* __restrict__ bv, const double* __restrict__ uin,
     const TE* __restrict__ e, double* __restrict__ uout, TR* __restrict__ r,
-    double* __restrict__ partials) {
-    const uint32_t col = global_index();
+    double* __restrict__ partials, int wpr) {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const Seg g = tiled_segment(int(logical_block()), wave, kBlock / 64, L.nI, L.nJ, wpr);
     double acc = 0;
-    if (col < uint32_t(L.plane)) {
-        const Nb nb = neighbours<ROWU>(col, L.nI, L.nJ);
+    {
+        const Seg& nb = g;
         const NbB<double> b8(nb);
         const NbB<TE> be(nb);
         const NbB<TR> br(nb);
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_update(
                       un(kk, b8.e, be.e), un(kk, b8.s, be.s), un(kk, b8.n, be.n)) +
                 tab(L.Tr, kk * nJ + nb.J) * (uc - um) + tab(L.Tr, (kk + 1) * nJ + nb.J) * (uc - up);
             const double rv = ldb<double>(layer(bv, kk, P8), b8.c) - h;
-            if (k < nz) {
+            if (k < nz && g.valid) {
                 if constexpr (HAS_E) stb<double>(layer_w(uout, kk, P8), b8.c, uc);
                 stb<TR>(layer_w(r, kk, PR), br.c, TR(rv));
                 acc += rv * rv;
@@ -221,17 +223,22 @@ void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
 template <typename TE, typename TR>
 int residual_update(const LevelView<double>& L, const double* b, const double* uin,
                     const TE* e, double* uout, TR* r, double* partials, hipStream_t s) {
-    const int nb = blocks_for(L.plane);
-    const bool rowu = L.nI % 64 == 0;
+    const int wpr = segments_per_row(L.nI);
+    const int nb = residual_update_blocks(L);
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
-#define MG_RES_LAUNCH(HE, RU) \
-    k_residual_update<TE, TR, NZ, HE, RU><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r, partials)
-        if (e) { if (rowu) MG_RES_LAUNCH(true, true); else MG_RES_LAUNCH(true, false); }
-        else { if (rowu) MG_RES_LAUNCH(false, true); else MG_RES_LAUNCH(false, false); }
-#undef MG_RES_LAUNCH
+        if (e)
+            k_residual_update<TE, TR, NZ, true><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r,
+                                                                     partials, wpr);
+        else
+            k_residual_update<TE, TR, NZ, false><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r,
+                                                                      partials, wpr);
     });
     return nb;
+}
+
+int residual_update_blocks(const LevelView<double>& L) {
+    return tiled_blocks(L.nJ, segments_per_row(L.nI), kBlock / 64);
 }
 
 int norm2_partials(const double* x, long long n, double* partials, hipStream_t s) {

@@ -234,7 +234,7 @@ void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin
     constexpr int PB = PairsPerBlock<T>::value;
     __shared__ T xch[PB][256];
     const PairOf p = pair_of_wave();
-    const Seg g = segment(int(logical_block()) * PB + p.pair, L.nI, L.nJ, wpr);
+    const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
     sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
 }
 
@@ -357,7 +357,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
     constexpr int PB = PairsPerBlock<T>::value;
     __shared__ T xch[PB][256];
     const PairOf p = pair_of_wave();
-    const Seg g = segment(int(logical_block()) * PB + p.pair, L.nI, L.nJ, wpr);
+    const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
     const NbB<T> b(g);
     const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
@@ -410,12 +410,10 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_stencil(LevelView<T> L,
     xb[t] = (T(1) - omega) * xb[t] + omega * h;
 }
 
-// Blocks of PB wavefront pairs covering every segment.
+// Blocks of PB wavefront pairs (row tiles of PB rows) covering every segment.
 template <typename T>
 inline int pair_blocks(const int nJ, const int wpr) {
-    const long long nseg = (long long)nJ * wpr;
-    constexpr int per = PairsPerBlock<T>::value;
-    return int((nseg + per - 1) / per);
+    return tiled_blocks(nJ, wpr, PairsPerBlock<T>::value);
 }
 
 }  // namespace

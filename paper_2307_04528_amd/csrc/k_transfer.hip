@@ -8,178 +8,145 @@
 
 namespace mgk {
 
-// Coarse levels with more columns than this restrict with one lane per coarse
-// column (registers reuse the vertical neighbours); smaller ones with one lane
-// per coarse cell (no per-lane layer chain, latency hidden by parallelism).
-#ifndef MG_RESTRICT_COLUMN_ABOVE
-#define MG_RESTRICT_COLUMN_ABOVE (1LL << 17)
-#endif
-
 namespace {
 using namespace dev;
 
-// Residual of the two or four children of coarse cell (Ic, Jc) in layer k,
-// summed. Children rows j0 and j1 = j0 + two (two = 0: one row, weight 0 on
-// the duplicate). xm/xc/xp are layer bases for k-1, k, k+1 (clamped; the
-// vertical coefficients are 0 at the bottom and top).
-template <typename T, bool HAS_X>
-__device__ __forceinline__ T restrict_cell(const LevelView<T>& F, const TransferView<T>& X,
-                                           const T* f, const T* x, int k, int Jc, int Ic) {
-    const int nI = F.nI, nJ = F.nJ, nz = F.nz;
-    const size_t P = size_t(F.plane);
-    const int j0 = X.child_first[Jc];
-    const int two = X.child_count[Jc] - 1;
-    const int j1 = j0 + two;
-    const T w1 = T(two);
-    const uint32_t i0 = 2 * Ic, i1 = i0 + 1;
-    const uint32_t r0 = uint32_t(j0) * nI, r1 = uint32_t(j1) * nI;
-    const T* fk = f + size_t(k) * P;
-    T acc = fk[r0 + i0] + fk[r0 + i1] + w1 * (fk[r1 + i0] + fk[r1 + i1]);
-    if constexpr (HAS_X) {
-        const uint32_t iw = (i0 == 0) ? nI - 1 : i0 - 1;
-        const uint32_t ie = (i1 == uint32_t(nI) - 1) ? 0 : i1 + 1;
-        const uint32_t rs = (j0 > 0) ? r0 - nI : r0;
-        const uint32_t rn = (j1 < nJ - 1) ? r1 + nI : r1;
-        const T* xk = x + size_t(k) * P;
-        const T* xm = x + size_t(k > 0 ? k - 1 : 0) * P;
-        const T* xp = x + size_t(k + 1 < nz ? k + 1 : k) * P;
-        const T* Mk = F.M + size_t(k) * P;
-        const T c00 = xk[r0 + i0], c01 = xk[r0 + i1], c10 = xk[r1 + i0], c11 = xk[r1 + i1];
-        const T tl0 = F.Tlam[k * nJ + j0], tl1 = F.Tlam[k * nJ + j1];
-        const T ts0 = F.Tth[k * (nJ + 1) + j0], tn0 = F.Tth[k * (nJ + 1) + j0 + 1];
-        const T ts1 = F.Tth[k * (nJ + 1) + j1], tn1 = F.Tth[k * (nJ + 1) + j1 + 1];
-        const T tb0 = F.Tr[k * nJ + j0], tt0 = F.Tr[(k + 1) * nJ + j0];
-        const T tb1 = F.Tr[k * nJ + j1], tt1 = F.Tr[(k + 1) * nJ + j1];
-        // a merged row's other row is its latitude neighbour
-        const T n00 = two ? c10 : xk[rn + i0], n01 = two ? c11 : xk[rn + i1];
-        const T s10 = two ? c00 : xk[rs + i0], s11 = two ? c01 : xk[rs + i1];
-        const T h0 = Mk[r0 + i0] * c00 +
-                     hdiff(tl0, ts0, tn0, c00, xk[r0 + iw], c01, xk[rs + i0], n00) +
-                     Mk[r0 + i1] * c01 +
-                     hdiff(tl0, ts0, tn0, c01, c00, xk[r0 + ie], xk[rs + i1], n01) +
-                     tb0 * ((c00 - xm[r0 + i0]) + (c01 - xm[r0 + i1])) +
-                     tt0 * ((c00 - xp[r0 + i0]) + (c01 - xp[r0 + i1]));
-        const T h1 = Mk[r1 + i0] * c10 +
-                     hdiff(tl1, ts1, tn1, c10, xk[r1 + iw], c11, s10, xk[rn + i0]) +
-                     Mk[r1 + i1] * c11 +
-                     hdiff(tl1, ts1, tn1, c11, c10, xk[r1 + ie], s11, xk[rn + i1]) +
-                     tb1 * ((c10 - xm[r1 + i0]) + (c11 - xm[r1 + i1])) +
-                     tt1 * ((c10 - xp[r1 + i0]) + (c11 - xp[r1 + i1]));
-        acc -= h0 + w1 * h1;
-    }
-    return acc;
+// Two adjacent values (the two longitude children of a coarse column).
+template <typename T>
+using pair_t = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ pair_t<T> ld2(gcptr base, uint32_t boff) {
+    return *(const __attribute__((address_space(1))) pair_t<T>*)(base + boff);
 }
 
-// One lane per coarse cell.
+// fc = R (f - H x), one wavefront per (row-aligned coarse segment, chunk of
+// kRestrictLayers layers), chunk-major. A lane owns one coarse column: its
+// two longitude children are adjacent, so each child row is one 2-value load;
+// the children rows, tables and transfer maps are wave-uniform. The x values
+// of the chunk's layers and the layers just outside it are loaded once.
+constexpr int kRestrictLayers = 4;
 template <typename T, bool HAS_X>
-__global__ __launch_bounds__(kBlock) void k_restrict_flat(LevelView<T> F, TransferView<T> X,
-                                                          const T* __restrict__ f,
-                                                          const T* __restrict__ x,
-                                                          T* __restrict__ fc, uint32_t nc) {
-    const uint32_t t = global_index();
-    if (t >= nc) return;
-    const uint32_t Pc = uint32_t(X.nIc) * X.nJc;
-    const int k = int(t / Pc);
-    const uint32_t colc = t - uint32_t(k) * Pc;
-    const int Jc = int(colc / uint32_t(X.nIc));
-    const int Ic = int(colc) - Jc * X.nIc;
-    fc[t] = restrict_cell<T, HAS_X>(F, X, f, x, k, Jc, Ic);
-}
-
-// One lane per coarse column, walking the layers (for large levels): the
-// four children's values of the layers below, at and above k stay in
-// registers, so each x value is loaded once per lane. ROWU: every wavefront
-// lies inside one coarse row, so the children rows and the tables are
-// wave-uniform.
-template <typename T, int NZ, bool ROWU>
-__global__ __launch_bounds__(kBlock) void k_restrict_column(LevelView<T> F, TransferView<T> X,
-                                                            const T* __restrict__ f,
-                                                            const T* __restrict__ x,
-                                                            T* __restrict__ fc) {
-    const uint32_t colc = global_index();
-    const uint32_t Pc = uint32_t(X.nIc) * X.nJc;
-    if (colc >= Pc) return;
+__global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, TransferView<T> X,
+                                                         const T* __restrict__ f,
+                                                         const T* __restrict__ x,
+                                                         T* __restrict__ fc, int wprc, int nsegc,
+                                                         int units) {
+    constexpr int DL = kRestrictLayers;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int unit = int(logical_block()) * (kBlock / 64) + wave;
+    if (unit >= units) return;   // wave-uniform
+    const int ch = unit / nsegc, seg = unit - ch * nsegc;
+    const Seg gc = segment(seg, X.nIc, X.nJc, wprc);
     const int nI = F.nI, nJ = F.nJ, nz = F.nz;
-    int Jc = int(colc / uint32_t(X.nIc));
-    if constexpr (ROWU) Jc = __builtin_amdgcn_readfirstlane(Jc);
-    const int Ic = int(colc) - Jc * X.nIc;
-    const int j0 = X.child_first[Jc];
-    const int two = X.child_count[Jc] - 1;  // 0 or 1
+    const int Jc = gc.J, Ic = int(gc.c) - Jc * X.nIc;
+    const int j0 = tab(X.child_first, Jc);
+    const int two = tab(X.child_count, Jc) - 1;   // 0 or 1
     const int j1 = j0 + two;
     const T w1 = T(two);
+    constexpr uint32_t S = sizeof(T);
     const uint32_t i0 = 2 * uint32_t(Ic), i1 = i0 + 1;
     const uint32_t iw = (i0 == 0) ? uint32_t(nI - 1) : i0 - 1;
     const uint32_t ie = (i1 == uint32_t(nI - 1)) ? 0u : i1 + 1;
     const uint32_t r0 = uint32_t(j0) * nI, r1 = uint32_t(j1) * nI;
     const uint32_t rs = (j0 > 0) ? r0 - nI : r0, rn = (j1 < nJ - 1) ? r1 + nI : r1;
-    constexpr uint32_t S = sizeof(T);
-    const uint32_t o00 = (r0 + i0) * S, o01 = (r0 + i1) * S, o10 = (r1 + i0) * S,
-                   o11 = (r1 + i1) * S;
-    const uint32_t ow0 = (r0 + iw) * S, oe0 = (r0 + ie) * S, ow1 = (r1 + iw) * S,
-                   oe1 = (r1 + ie) * S;
-    const uint32_t os0 = (rs + i0) * S, os1 = (rs + i1) * S, on0 = (rn + i0) * S,
-                   on1 = (rn + i1) * S;
-    const uint64_t Pb = uint64_t(F.plane) * S, Pcb = uint64_t(Pc) * S;
-    const uint32_t oc = colc * S;
-    T m00 = 0, m01 = 0, m10 = 0, m11 = 0;
-    gcptr x0 = layer(x, 0, Pb);
-    T c00 = ldb<T>(x0, o00), c01 = ldb<T>(x0, o01), c10 = ldb<T>(x0, o10), c11 = ldb<T>(x0, o11);
+    const uint32_t o0 = (r0 + i0) * S, o1 = (r1 + i0) * S;
+    const uint64_t Pb = uint64_t(F.plane) * S, Pcb = uint64_t(X.nIc) * X.nJc * S;
+    const uint32_t oc = gc.c * S;
+    const int k0 = ch * DL;
+    T out[DL];
+    if constexpr (!HAS_X) {
 #pragma unroll
-    for (int k = 0; k < NZ; ++k) {
-        const int kk = clampk(k, nz), kp = clampk(k + 1, nz);
-        gcptr fk = layer(f, kk, Pb), Mk = layer(F.M, kk, Pb), xk = layer(x, kk, Pb),
-              xp = layer(x, kp, Pb);
-        const T p00 = ldb<T>(xp, o00), p01 = ldb<T>(xp, o01), p10 = ldb<T>(xp, o10),
-                p11 = ldb<T>(xp, o11);
-        const T tl0 = tab(F.Tlam, kk * nJ + j0), tl1 = tab(F.Tlam, kk * nJ + j1);
-        const T ts0 = tab(F.Tth, kk * (nJ + 1) + j0), tn0 = tab(F.Tth, kk * (nJ + 1) + j0 + 1);
-        const T ts1 = tab(F.Tth, kk * (nJ + 1) + j1), tn1 = tab(F.Tth, kk * (nJ + 1) + j1 + 1);
-        const T tb0 = tab(F.Tr, kk * nJ + j0), tt0 = tab(F.Tr, (kk + 1) * nJ + j0);
-        const T tb1 = tab(F.Tr, kk * nJ + j1), tt1 = tab(F.Tr, (kk + 1) * nJ + j1);
-        // a merged row's other row is its latitude neighbour
-        const T n00 = two ? c10 : ldb<T>(xk, on0), n01 = two ? c11 : ldb<T>(xk, on1);
-        const T s10 = two ? c00 : ldb<T>(xk, os0), s11 = two ? c01 : ldb<T>(xk, os1);
-        const T h0 = ldb<T>(Mk, o00) * c00 +
-                     hdiff(tl0, ts0, tn0, c00, ldb<T>(xk, ow0), c01, ldb<T>(xk, os0), n00) +
-                     ldb<T>(Mk, o01) * c01 +
-                     hdiff(tl0, ts0, tn0, c01, c00, ldb<T>(xk, oe0), ldb<T>(xk, os1), n01) +
-                     tb0 * ((c00 - m00) + (c01 - m01)) + tt0 * ((c00 - p00) + (c01 - p01));
-        const T h1 = ldb<T>(Mk, o10) * c10 +
-                     hdiff(tl1, ts1, tn1, c10, ldb<T>(xk, ow1), c11, s10, ldb<T>(xk, on0)) +
-                     ldb<T>(Mk, o11) * c11 +
-                     hdiff(tl1, ts1, tn1, c11, c10, ldb<T>(xk, oe1), s11, ldb<T>(xk, on1)) +
-                     tb1 * ((c10 - m10) + (c11 - m11)) + tt1 * ((c10 - p10) + (c11 - p11));
-        const T acc = ldb<T>(fk, o00) + ldb<T>(fk, o01) +
-                      w1 * (ldb<T>(fk, o10) + ldb<T>(fk, o11)) - (h0 + w1 * h1);
-        if (k < nz) stb<T>(layer_w(fc, kk, Pcb), oc, acc);
-        m00 = c00; m01 = c01; m10 = c10; m11 = c11;
-        c00 = p00; c01 = p01; c10 = p10; c11 = p11;
+        for (int d = 0; d < DL; ++d) {
+            gcptr fk = layer(f, clampk(k0 + d, nz), Pb);
+            const pair_t<T> a = ld2<T>(fk, o0), b = ld2<T>(fk, o1);
+            out[d] = a.x + a.y + w1 * (b.x + b.y);
+        }
+    } else {
+        const uint32_t ow0 = (r0 + iw) * S, oe0 = (r0 + ie) * S, ow1 = (r1 + iw) * S,
+                       oe1 = (r1 + ie) * S, os = (rs + i0) * S, on = (rn + i0) * S;
+        // children of the layers k0-1 .. k0+DL (clamped; the vertical couplings
+        // are 0 at the bottom and top)
+        pair_t<T> c0[DL + 2], c1[DL + 2];
+#pragma unroll
+        for (int d = 0; d < DL + 2; ++d) {
+            const int kk = k0 - 1 + d;
+            gcptr xk = layer(x, kk < 0 ? 0 : clampk(kk, nz), Pb);
+            c0[d] = ld2<T>(xk, o0);
+            c1[d] = ld2<T>(xk, o1);
+        }
+#pragma unroll
+        for (int d = 0; d < DL; ++d) {
+            const int kk = clampk(k0 + d, nz);
+            gcptr fk = layer(f, kk, Pb), Mk = layer(F.M, kk, Pb), xk = layer(x, kk, Pb);
+            const pair_t<T> fa = ld2<T>(fk, o0), fb = ld2<T>(fk, o1);
+            const pair_t<T> ma = ld2<T>(Mk, o0), mb = ld2<T>(Mk, o1);
+            const pair_t<T> xs = ld2<T>(xk, os), xn = ld2<T>(xk, on);
+            const T xw0 = ldb<T>(xk, ow0), xe0 = ldb<T>(xk, oe0), xw1 = ldb<T>(xk, ow1),
+                    xe1 = ldb<T>(xk, oe1);
+            const pair_t<T> a = c0[d + 1], b = c1[d + 1];
+            const pair_t<T> am = c0[d], bm = c1[d], ap = c0[d + 2], bp = c1[d + 2];
+            const T tl0 = tab(F.Tlam, kk * nJ + j0), tl1 = tab(F.Tlam, kk * nJ + j1);
+            const T ts0 = tab(F.Tth, kk * (nJ + 1) + j0), tn0 = tab(F.Tth, kk * (nJ + 1) + j0 + 1);
+            const T ts1 = tab(F.Tth, kk * (nJ + 1) + j1), tn1 = tab(F.Tth, kk * (nJ + 1) + j1 + 1);
+            const T tb0 = tab(F.Tr, kk * nJ + j0), tt0 = tab(F.Tr, (kk + 1) * nJ + j0);
+            const T tb1 = tab(F.Tr, kk * nJ + j1), tt1 = tab(F.Tr, (kk + 1) * nJ + j1);
+            // a merged row's other row is its latitude neighbour
+            const T n00 = two ? b.x : xn.x, n01 = two ? b.y : xn.y;
+            const T s10 = two ? a.x : xs.x, s11 = two ? a.y : xs.y;
+            const T h0 = ma.x * a.x + hdiff(tl0, ts0, tn0, a.x, xw0, a.y, xs.x, n00) +
+                         ma.y * a.y + hdiff(tl0, ts0, tn0, a.y, a.x, xe0, xs.y, n01) +
+                         tb0 * ((a.x - am.x) + (a.y - am.y)) + tt0 * ((a.x - ap.x) + (a.y - ap.y));
+            const T h1 = mb.x * b.x + hdiff(tl1, ts1, tn1, b.x, xw1, b.y, s10, xn.x) +
+                         mb.y * b.y + hdiff(tl1, ts1, tn1, b.y, b.x, xe1, s11, xn.y) +
+                         tb1 * ((b.x - bm.x) + (b.y - bm.y)) + tt1 * ((b.x - bp.x) + (b.y - bp.y));
+            out[d] = fa.x + fa.y + w1 * (fb.x + fb.y) - (h0 + w1 * h1);
+        }
     }
+#pragma unroll
+    for (int d = 0; d < DL; ++d)
+        if (k0 + d < nz && gc.valid) stb<T>(layer_w(fc, k0 + d, Pcb), oc, out[d]);
 }
 
-// x += P xc, one lane per fine cell: bilinear interpolation (3/4, 1/4 in
-// longitude; the row weights of the map in latitude).
+// x += P xc: bilinear interpolation (3/4, 1/4 in longitude; the row weights
+// of the map in latitude). One wavefront per (row-aligned segment, chunk of
+// kProlongLayers layers), chunk-major so that each XCD streams a band of rows
+// of one chunk: the fine row's coarse rows and weights are wave-uniform, the
+// per-lane coarse columns are computed once, and the loads of the whole chunk
+// are independent and issued together.
+constexpr int kProlongLayers = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, TransferView<T> X,
                                                         const T* __restrict__ xc,
-                                                        T* __restrict__ x, uint32_t n) {
-    const uint32_t t = global_index();
-    if (t >= n) return;
-    const uint32_t P = uint32_t(F.plane);
-    const int k = int(t / P);
-    const uint32_t col = t - uint32_t(k) * P;
-    const int j = int(col / uint32_t(F.nI));
-    const int i = int(col) - j * F.nI;
-    const int nIc = X.nIc;
-    const int J0 = X.prow[2 * j], J1 = X.prow[2 * j + 1];
-    const T w0 = X.pw[2 * j], w1 = X.pw[2 * j + 1];
+                                                        T* __restrict__ x, int wpr, int nseg,
+                                                        int units) {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int unit = int(logical_block()) * (kBlock / 64) + wave;
+    if (unit >= units) return;   // wave-uniform
+    const int ch = unit / nseg, seg = unit - ch * nseg;
+    const Seg g = segment(seg, F.nI, F.nJ, wpr);
+    const int j = g.J, i = int(g.c) - j * F.nI, nIc = X.nIc;
+    const int J0 = tab(X.prow, 2 * j), J1 = tab(X.prow, 2 * j + 1);
+    const T w0 = tab(X.pw, 2 * j), w1 = tab(X.pw, 2 * j + 1);
     const int I = i >> 1;
     const int In = (i & 1) ? (I + 1 == nIc ? 0 : I + 1) : (I == 0 ? nIc - 1 : I - 1);
-    const T* lay = xc + size_t(k) * nIc * X.nJc;
-    const T* c0 = lay + J0 * nIc;
-    const T* c1 = lay + J1 * nIc;
+    constexpr uint32_t S = sizeof(T);
+    const uint32_t o0 = uint32_t(J0 * nIc + I) * S, o0n = uint32_t(J0 * nIc + In) * S;
+    const uint32_t o1 = uint32_t(J1 * nIc + I) * S, o1n = uint32_t(J1 * nIc + In) * S;
+    const uint32_t ox = g.c * S;
+    const uint64_t Pb = uint64_t(F.plane) * S, Pcb = uint64_t(nIc) * X.nJc * S;
+    const int nz = F.nz, k0 = ch * kProlongLayers;
     const T a = T(0.75), b = T(0.25);
-    x[t] += w0 * (a * c0[I] + b * c0[In]) + w1 * (a * c1[I] + b * c1[In]);
+    T v[kProlongLayers];
+#pragma unroll
+    for (int d = 0; d < kProlongLayers; ++d) {
+        const int kk = clampk(k0 + d, nz);
+        gcptr ck = layer(xc, kk, Pcb);
+        v[d] = ldb<T>(layer(x, kk, Pb), ox) + w0 * (a * ldb<T>(ck, o0) + b * ldb<T>(ck, o0n)) +
+               w1 * (a * ldb<T>(ck, o1) + b * ldb<T>(ck, o1n));
+    }
+#pragma unroll
+    for (int d = 0; d < kProlongLayers; ++d)
+        if (k0 + d < nz && g.valid) stb<T>(layer_w(x, k0 + d, Pb), ox, v[d]);
 }
 
 // xc = P^T x, one lane per coarse cell.
@@ -249,27 +216,24 @@ __global__ __launch_bounds__(kBlock) void k_inject_residual_adj(LevelView<T> F,
 template <typename T>
 void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T* f,
                        const T* x, T* fc, hipStream_t s) {
-    const long long Pc = (long long)X.nIc * X.nJc;
-    if (x && Pc > MG_RESTRICT_COLUMN_ABOVE) {
-        with_nz(F.nz, [&](auto nzc) {
-            constexpr int NZ = decltype(nzc)::value;
-            if (X.nIc % 64 == 0)
-                k_restrict_column<T, NZ, true><<<blocks_for(Pc), kBlock, 0, s>>>(F, X, f, x, fc);
-            else
-                k_restrict_column<T, NZ, false><<<blocks_for(Pc), kBlock, 0, s>>>(F, X, f, x, fc);
-        });
-        return;
-    }
-    const long long nc = Pc * F.nz;
-    if (x) k_restrict_flat<T, true><<<blocks_for(nc), kBlock, 0, s>>>(F, X, f, x, fc, uint32_t(nc));
-    else k_restrict_flat<T, false><<<blocks_for(nc), kBlock, 0, s>>>(F, X, f, x, fc, uint32_t(nc));
+    const int wprc = segments_per_row(X.nIc);
+    const int nsegc = X.nJc * wprc;
+    const int units = nsegc * ((F.nz + kRestrictLayers - 1) / kRestrictLayers);
+    constexpr int waves = kBlock / 64;
+    const int nb = (units + waves - 1) / waves;
+    if (x) k_restrict_seg<T, true><<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
+    else k_restrict_seg<T, false><<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
 }
 
 template <typename T>
 void prolong_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T* x,
                  hipStream_t s) {
-    const long long n = F.plane * F.nz;
-    k_prolong_add<T><<<blocks_for(n), kBlock, 0, s>>>(F, X, xc, x, uint32_t(n));
+    const int wpr = segments_per_row(F.nI);
+    const int nseg = F.nJ * wpr;
+    const int units = nseg * ((F.nz + kProlongLayers - 1) / kProlongLayers);
+    constexpr int waves = kBlock / 64;
+    k_prolong_add<T><<<(units + waves - 1) / waves, kBlock, 0, s>>>(F, X, xc, x, wpr, nseg,
+                                                                    units);
 }
 
 template <typename T>

@@ -127,6 +127,8 @@ void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStrea
 template <typename TE, typename TR>
 int residual_update(const LevelView<double>& L, const double* b, const double* uin,
                     const TE* e, double* uout, TR* r, double* partials, hipStream_t s);
+// Blocks (hence partial sums) residual_update launches for level L.
+int residual_update_blocks(const LevelView<double>& L);
 
 // Per-block partial sums of x^2.
 int norm2_partials(const double* x, long long n, double* partials, hipStream_t s);

@@ -652,7 +652,8 @@ mg_status build(mg_handle* h, const double* alpha) {
         }
     }
     DevLevel& f = h->lv[0];
-    h->max_partials = std::max(mgk::blocks_for(f.plane), 8192);
+    h->max_partials = std::max({mgk::residual_update_blocks(view<double>(f)),
+                                mgk::blocks_for(f.plane), 8192});
     MG_TRY(dalloc(h, &h->partials, size_t(h->max_partials)));
     MG_TRY(dalloc(h, &h->scalar, 1));
     MG_TRY(dalloc(h, &h->u_alt, f.n));

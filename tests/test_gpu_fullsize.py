@@ -1,0 +1,83 @@
+"""Parity at the full sizes of the benchmark workloads, through the same
+entry points and launch configuration that bench.py times.
+
+  * shell1024x768x70 (55M cells): one FP32 and one FP64 V-cycle against the
+    oracle's, element by element over the whole field; one finest-level
+    sweep from an iterate (the benchmark's dominant kernel) and one from
+    zero against the oracle's; the mixed solve to relative residual 1e-8,
+    with ||b - H u|| / ||b|| of the returned u recomputed by the oracle on
+    the host.
+  * shell2560x1920x70 (344M cells): the mixed solve to 1e-8, its residual
+    recomputed by the oracle on the host (a whole oracle V-cycle at this size
+    is too slow for a test; the per-cycle parity is covered above).
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import shellgen
+import oracle
+from gpu_util import log, t, n, solver_for, rel_inf, rel2, opts_of
+
+pytestmark = pytest.mark.gpu
+
+BENCH = shellgen.workload("shell1024x768x70")
+LARGEST = shellgen.workload("shell2560x1920x70")
+
+
+@functools.lru_cache(maxsize=1)
+def bench_levels():
+    log("[oracle] hierarchy of shell1024x768x70")
+    return oracle.build_hierarchy(BENCH, shellgen.alpha(BENCH))
+
+
+@functools.lru_cache(maxsize=1)
+def bench_vcycle_ref():
+    log("[oracle] one V(2,2) cycle on shell1024x768x70")
+    return oracle.vcycle(bench_levels(), shellgen.rhs(BENCH), opts_of(BENCH))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_vcycle_full_field(prec):
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec)
+    got = n(S.vcycle(t(shellgen.rhs(BENCH))))
+    ref = bench_vcycle_ref()
+    err = rel_inf(got, ref) if prec == "fp64" else rel2(got, ref)
+    log(f"full-size vcycle {prec}: {err:.2e}")
+    assert err < (1e-12 if prec == "fp64" else 1e-4)
+    S.close()
+
+
+def test_bench_finest_sweeps_full_field():
+    L = bench_levels()
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision="mixed")
+    rng = np.random.default_rng(41)
+    f = rng.uniform(-1, 1, BENCH.shape)
+    x = rng.uniform(-1, 1, BENCH.shape)
+    got0 = n(S.level_sweep(0, t(f)))
+    got = n(S.level_sweep(0, t(f), t(x)))
+    ref0 = oracle.sweep_from_zero(L[0], f, 0.8)
+    ref = oracle.sweep(L[0], x, f, 0.8)
+    log(f"full-size finest sweeps: from zero {rel_inf(got0, ref0):.2e}, "
+        f"from an iterate {rel_inf(got, ref):.2e}")
+    assert rel_inf(got0, ref0) < 2e-5
+    assert rel_inf(got, ref) < 2e-5
+    S.close()
+
+
+@pytest.mark.parametrize("sh", [BENCH, LARGEST], ids=lambda s: s.name)
+def test_mixed_solve_residual_checked_on_host(sh):
+    log(f"[gpu] mixed solve of {sh.name} ({sh.n} cells)")
+    a, b = shellgen.alpha(sh), shellgen.rhs(sh)
+    S = solver_for(sh, a, precision="mixed")
+    u, st = S.solve(t(b), tol=1e-8)
+    u = n(u)
+    S.close()
+    log(f"  gpu: {st.iters} iterations, relres {st.relres:.3e}")
+    fine = oracle.build_hierarchy(sh, a, levels=1)[0]
+    r = b - oracle.apply(fine, u)
+    relres = float(np.linalg.norm(r.ravel()) / np.linalg.norm(b.ravel()))
+    log(f"  oracle residual of the returned u: {relres:.3e}")
+    assert relres <= 1e-8
+    assert relres == pytest.approx(st.relres, rel=1e-3)
