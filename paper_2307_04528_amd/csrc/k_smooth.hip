@@ -28,10 +28,13 @@ namespace mgk {
 #define MG_CHUNK32 6
 #endif
 #ifndef MG_CHUNK64
-#define MG_CHUNK64 4
+#define MG_CHUNK64 2
 #endif
-#ifndef MG_CHUNK_SMALL
-#define MG_CHUNK_SMALL 6
+#ifndef MG_CHUNK_SMALL32
+#define MG_CHUNK_SMALL32 6
+#endif
+#ifndef MG_CHUNK_SMALL64
+#define MG_CHUNK_SMALL64 2
 #endif
 #ifndef MG_PAIRS32
 #define MG_PAIRS32 2
@@ -41,6 +44,12 @@ namespace mgk {
 #endif
 #ifndef MG_KEEPX64
 #define MG_KEEPX64 0
+#endif
+#ifndef MG_RAW32
+#define MG_RAW32 0
+#endif
+#ifndef MG_RAW64
+#define MG_RAW64 1
 #endif
 
 namespace {
@@ -52,16 +61,29 @@ struct ColumnWaves {
     static constexpr int value = std::is_same<T, float>::value ? MG_SMOOTH_WAVES32
                                                                 : MG_SMOOTH_WAVES64;
 };
-// Layers per prefetch chunk on levels large enough to fill the GPU.
+// Layers per prefetch chunk on levels large enough to fill the GPU, and on
+// the smaller levels (where the per-column latency chain sets the time).
 template <typename T>
 struct ChunkDepth {
     static constexpr int value = std::is_same<T, float>::value ? MG_CHUNK32 : MG_CHUNK64;
+    static constexpr int small =
+        std::is_same<T, float>::value ? MG_CHUNK_SMALL32 : MG_CHUNK_SMALL64;
 };
 // Wavefront pairs per block of the sweep kernels (the pair's exchange is a
 // block barrier, so fewer pairs per block couple fewer columns).
 template <typename T>
 struct PairsPerBlock {
     static constexpr int value = std::is_same<T, float>::value ? MG_PAIRS32 : MG_PAIRS64;
+};
+
+// Prefetch the raw loads of a chunk (FP64: the loads then stay in flight
+// while the previous chunk is solved) or combine them into the chunk's
+// right-hand sides at fetch time (FP32: fewer registers, more wavefronts per
+// SIMD, which hides the latency better at this size). Both measured.
+template <typename T>
+struct RawPrefetch {
+    static constexpr bool value = std::is_same<T, float>::value ? (MG_RAW32 != 0)
+                                                                : (MG_RAW64 != 0);
 };
 
 // Steps of one wavefront of a pair for the layer bucket NZ.
@@ -73,7 +95,11 @@ constexpr int padded_steps() { return ((half_steps<NZ>() + D - 1) / D) * D; }
 // Twisted solve z = H_z^{-1} s of one column by one wavefront of a pair.
 //   top          : false for the bottom wavefront, true for the top (uniform)
 //   xch          : 256 values of LDS private to the pair
-//   src(t, kk)   : issues the loads of layer kk (step t), returns s_kk
+//   fetch(t, kk) : issues the loads of layer kk (step t) and returns them
+//                  raw (any struct), with no arithmetic on them, so that a
+//                  chunk's loads stay in flight while the previous chunk is
+//                  solved
+//   comb(t, kk, raw): s_kk from the fetched values
 //   inv(kk)      : the stored twisted pivot of layer kk
 //   cpl(F)       : Tr_F, the vertical coupling across face F (below layer F)
 //   fsink(t, kk, s): s of one of this wavefront's layers is available
@@ -85,16 +111,23 @@ constexpr int padded_steps() { return ((half_steps<NZ>() + D - 1) / D) * D; }
 // Step t is layer t (bottom) or nz-1-t (top). Steps beyond a wavefront's
 // layers compute on clamped data and reach neither fsink nor sink. Every
 // thread of the block must call this (one block barrier inside).
-template <typename T, int NZ, int D, bool BL, class Src, class Inv, class Cpl, class FSink,
-          class BLoad, class Sink>
-__device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Src src, Inv inv,
-                                               Cpl cpl, FSink fsink, BLoad bload, Sink sink) {
+template <typename T, int NZ, int D, bool BL, class Fetch, class Comb, class Inv, class Cpl,
+          class FSink, class BLoad, class Sink>
+__device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Fetch fetch, Comb comb,
+                                               Inv inv, Cpl cpl, FSink fsink, BLoad bload,
+                                               Sink sink) {
     constexpr int NP = padded_steps<NZ, D>();
     constexpr int NC = NP / D;
+    using Raw = decltype(fetch(0, 0));
     const int m = nz >> 1, tm = nz - 1 - m;
     const int nrec = top ? tm : m;   // steps eliminated by this wavefront
     T y[NP], cb[NP];
-    T bs[2][D], bp[2][D];
+    // RAW: buffer the fetched values and combine them when the chunk is
+    // solved; otherwise combine at fetch time and buffer s (fewer registers)
+    constexpr bool RAW = RawPrefetch<T>::value;
+    Raw br[2][RAW ? D : 1];
+    T bs[2][RAW ? 1 : D];
+    T bp[2][D];
     auto lay = [&](int t) {
         const int k = top ? nz - 1 - t : t;
         return k < 0 ? 0 : (k < nz ? k : nz - 1);
@@ -103,7 +136,8 @@ __device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Src src
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int t = c * D + d, kk = lay(t);
-            bs[buf][d] = src(t, kk);
+            if constexpr (RAW) br[buf][d] = fetch(t, kk);
+            else bs[buf][d] = comb(t, kk, fetch(t, kk));
             bp[buf][d] = inv(kk);
         }
     };
@@ -116,7 +150,10 @@ __device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Src src
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             const int t = c * D + d, kk = lay(t);
-            const T s = bs[c & 1][d], ip = bp[c & 1][d];
+            T s;
+            if constexpr (RAW) s = comb(t, kk, br[c & 1][d]);
+            else s = bs[c & 1][d];
+            const T ip = bp[c & 1][d];
             if (t < nrec || (top && t == tm)) fsink(t, kk, s);
             // couplings to the layer eliminated before this one and to the
             // one after it
@@ -172,6 +209,13 @@ __device__ __forceinline__ void twisted_column(int nz, bool top, T* xch, Src src
     }
 }
 
+// The raw loads of one layer of a sweep: the right-hand side, and the
+// iterate at the cell (c) and its four horizontal neighbours.
+template <typename T>
+struct StencilRaw {
+    T f, c, w, e, s, n;
+};
+
 // Keep the old iterate of a column in registers between the two passes
 // (FP32), or load it again in the back-substitution (FP64, where keeping it
 // would cost the second wavefront per SIMD).
@@ -192,14 +236,25 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
     const T keep = T(1) - omega;
     constexpr bool KX = HAS_X && KeepX<T>::value;
     T xk[KX ? padded_steps<NZ, D>() : 1];
-    auto src = [&](int t, int kk) -> T {
-        T s = ldb<T>(layer(f, kk, Pb), b.c);
+    auto fetch = [&](int, int kk) {
+        StencilRaw<T> r{};
+        r.f = ldb<T>(layer(f, kk, Pb), b.c);
         if constexpr (HAS_X) {
             gcptr xl = layer(xin, kk, Pb);
-            s += tab(L.Tlam, kk * nJ + J) * (ldb<T>(xl, b.w) + ldb<T>(xl, b.e)) +
-                 tab(L.Tth, kk * (nJ + 1) + J) * ldb<T>(xl, b.s) +
-                 tab(L.Tth, kk * (nJ + 1) + J + 1) * ldb<T>(xl, b.n);
-            if constexpr (KX) xk[t] = ldb<T>(xl, b.c);
+            r.w = ldb<T>(xl, b.w);
+            r.e = ldb<T>(xl, b.e);
+            r.s = ldb<T>(xl, b.s);
+            r.n = ldb<T>(xl, b.n);
+            if constexpr (KX) r.c = ldb<T>(xl, b.c);
+        }
+        return r;
+    };
+    auto comb = [&](int t, int kk, const StencilRaw<T>& r) -> T {
+        T s = r.f;
+        if constexpr (HAS_X) {
+            s += tab(L.Tlam, kk * nJ + J) * (r.w + r.e) + tab(L.Tth, kk * (nJ + 1) + J) * r.s +
+                 tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
+            if constexpr (KX) xk[t] = r.c;
         }
         return s;
     };
@@ -213,7 +268,8 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
         else if constexpr (HAS_X) out += keep * e;
         if (g.valid) stb<T>(layer_w(xout, kk, Pb), b.c, out);
     };
-    twisted_column<T, NZ, D, HAS_X && !KX>(L.nz, top, xch, src, inv, cpl, fsink, bload, sink);
+    twisted_column<T, NZ, D, HAS_X && !KX>(L.nz, top, xch, fetch, comb, inv, cpl, fsink, bload,
+                                            sink);
 }
 
 // Wavefront w of a block: pair w/2 of the block, bottom (even w) or top.
@@ -301,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     const int col = p.pair * 64 + int(threadIdx.x & 63u);
     const bool active = col < plane;
     const Nb b = neighbours<false>(active ? uint32_t(col) : 0u, L.nI, nJ);
-    constexpr int D = MG_CHUNK_SMALL;
+    constexpr int D = ChunkDepth<T>::small;
     constexpr int NP = padded_steps<NZ, D>();
     const T keep = T(1) - omega;
     const int m = nz >> 1, nown = p.top ? nz - m : m;   // layers this wavefront writes
@@ -316,19 +372,29 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
         // loop into hundreds of registers (the empty asm emits nothing)
         int pl = plane, nj = nJ;
         asm volatile("" : "+s"(pl), "+s"(nj));
-        auto src = [&](int t, int kk) -> T {
+        auto fetch = [&](int, int kk) {
             const T* xl = sx + kk * pl;
-            xk[t] = xl[b.c];
-            return sf[kk * pl + b.c] + stl[kk * nj + b.J] * (xl[b.w] + xl[b.e]) +
-                   sth[kk * (nj + 1) + b.J] * xl[b.s] + sth[kk * (nj + 1) + b.J + 1] * xl[b.n];
+            StencilRaw<T> r;
+            r.f = sf[kk * pl + b.c];
+            r.c = xl[b.c];
+            r.w = xl[b.w];
+            r.e = xl[b.e];
+            r.s = xl[b.s];
+            r.n = xl[b.n];
+            return r;
+        };
+        auto comb = [&](int t, int kk, const StencilRaw<T>& r) -> T {
+            xk[t] = r.c;
+            return r.f + stl[kk * nj + b.J] * (r.w + r.e) + sth[kk * (nj + 1) + b.J] * r.s +
+                   sth[kk * (nj + 1) + b.J + 1] * r.n;
         };
         auto inv = [&](int kk) -> T { return sp[kk * pl + b.c]; };
         auto cpl = [&](int F) -> T { return str[F * nj + b.J]; };
         auto fsink = [](int, int, T) {};
         auto bload = [](int) -> T { return T(0); };
         auto sink = [&](int t, int, T z, T) { xk[t] = omega * z + keep * xk[t]; };
-        twisted_column<T, NZ, D, false>(nz, p.top, xch + p.pair * 256, src, inv, cpl, fsink,
-                                        bload, sink);
+        twisted_column<T, NZ, D, false>(nz, p.top, xch + p.pair * 256, fetch, comb, inv, cpl,
+                                        fsink, bload, sink);
         __syncthreads();   // every lane has read the old iterate
         if (active) {
 #pragma unroll
@@ -362,16 +428,26 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
     const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
-    auto src = [&](int, int kk) -> T {
-        T s = ldb<T>(layer(xb, kk, Pb), b.c);
+    auto fetch = [&](int, int kk) {
+        StencilRaw<T> r{};
+        r.f = ldb<T>(layer(xb, kk, Pb), b.c);
         if constexpr (HAS_Z) {
             gcptr zk = layer(zin, kk, Pb);
-            const T h = tab(L.Tlam, kk * nJ + J) * (ldb<T>(zk, b.w) + ldb<T>(zk, b.e)) +
-                        tab(L.Tth, kk * (nJ + 1) + J) * ldb<T>(zk, b.s) +
-                        tab(L.Tth, kk * (nJ + 1) + J + 1) * ldb<T>(zk, b.n);
-            s = keep * s + omega * h;
+            r.w = ldb<T>(zk, b.w);
+            r.e = ldb<T>(zk, b.e);
+            r.s = ldb<T>(zk, b.s);
+            r.n = ldb<T>(zk, b.n);
         }
-        return s;
+        return r;
+    };
+    auto comb = [&](int, int kk, const StencilRaw<T>& r) -> T {
+        if constexpr (HAS_Z) {
+            const T h = tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
+                        tab(L.Tth, kk * (nJ + 1) + J) * r.s +
+                        tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
+            return keep * r.f + omega * h;
+        }
+        return r.f;
     };
     auto inv = [&](int kk) -> T { return ldb<T>(layer(L.invp, kk, Pb), b.c); };
     auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
@@ -389,7 +465,8 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
             stb<T>(layer_w(fb, kk, Pb), b.c, fo);
         }
     };
-    twisted_column<T, NZ, D, ACC>(L.nz, p.top, xch[p.pair], src, inv, cpl, fsink, bload, sink);
+    twisted_column<T, NZ, D, ACC>(L.nz, p.top, xch[p.pair], fetch, comb, inv, cpl, fsink, bload,
+                                  sink);
 }
 
 // xb = (1-omega) xb + omega sum_h T_h z_nb, one lane per cell.
@@ -426,7 +503,7 @@ void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, h
     const bool small = L.plane < kSmallLevelColumns;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
-        constexpr int DB = ChunkDepth<T>::value, DS = MG_CHUNK_SMALL;
+        constexpr int DB = ChunkDepth<T>::value, DS = ChunkDepth<T>::small;
 #define MG_SMOOTH_LAUNCH(D, HX) \
     k_smooth<T, NZ, D, HX><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr)
         if (small) {
@@ -469,8 +546,8 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
     const int wpr = segments_per_row(L.nI);
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
-        k_coarse_solve<T, NZ, MG_CHUNK_SMALL><<<1, kBlock, 0, s>>>(L, f, xa, xb, omega, sweeps,
-                                                                   wpr);
+        k_coarse_solve<T, NZ, ChunkDepth<T>::small><<<1, kBlock, 0, s>>>(L, f, xa, xb, omega,
+                                                                         sweeps, wpr);
     });
     return (sweeps & 1) ? 0 : 1;
 }
