@@ -282,7 +282,10 @@ __device__ __forceinline__ PairOf pair_of_wave() {
     return {wave >> 1, (wave & 1) != 0};
 }
 
-template <typename T, int NZ, int D, bool HAS_X>
+// LARGE: the level has at least kSmallLevelColumns columns. The flag changes
+// no code; it keeps the sweeps of the bandwidth-bound large levels a symbol
+// of their own, apart from the latency-bound small levels, in profiles.
+template <typename T, int NZ, int D, bool HAS_X, bool LARGE>
 __global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
 __attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
 void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
@@ -504,12 +507,12 @@ void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, h
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int DB = ChunkDepth<T>::value, DS = ChunkDepth<T>::small;
-#define MG_SMOOTH_LAUNCH(D, HX) \
-    k_smooth<T, NZ, D, HX><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr)
+#define MG_SMOOTH_LAUNCH(D, HX, LG) \
+    k_smooth<T, NZ, D, HX, LG><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr)
         if (small) {
-            if (xin) MG_SMOOTH_LAUNCH(DS, true); else MG_SMOOTH_LAUNCH(DS, false);
+            if (xin) MG_SMOOTH_LAUNCH(DS, true, false); else MG_SMOOTH_LAUNCH(DS, false, false);
         } else {
-            if (xin) MG_SMOOTH_LAUNCH(DB, true); else MG_SMOOTH_LAUNCH(DB, false);
+            if (xin) MG_SMOOTH_LAUNCH(DB, true, true); else MG_SMOOTH_LAUNCH(DB, false, true);
         }
 #undef MG_SMOOTH_LAUNCH
     });
