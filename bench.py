@@ -74,7 +74,7 @@ def measured_traffic(workload, cls):
     return rec["bytes_per_launch"], rec["kernel"]
 
 
-def cpu_baseline(shell, iters_gpu):
+def cpu_baseline(shell, iters_gpu, smooth):
     """The oracle, untuned, on the host: one outer iteration (one V-cycle and
     one FP64 residual) of the same workload, scaled by the GPU's iteration
     count to a time-to-solution."""
@@ -87,6 +87,7 @@ def cpu_baseline(shell, iters_gpu):
     oracle.column_solve(L[0], np.zeros(shell.shape))   # pivots cached
     t_setup = time.perf_counter() - t0
     opt = oracle.Options(nu_pre=shell.nu_pre, nu_post=shell.nu_post)
+    opt.smooth_lo, opt.smooth_hi = smooth if smooth else (0.0, 0.0)
     t0 = time.perf_counter()
     r = b - oracle.apply(L[0], np.zeros(shell.shape))
     u = oracle.vcycle(L, r, opt)
@@ -113,7 +114,14 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--smooth-interval", default="0.333333333333333333,2", metavar="LO,HI",
+                    help="per-sweep damping factors from the Chebyshev nodes of [LO, HI] "
+                         "(default 1/3,2, the library default); 'none': every sweep "
+                         "uses omega 0.8")
     args = ap.parse_args()
+    smooth = None
+    if args.smooth_interval != "none":
+        smooth = tuple(float(v) for v in args.smooth_interval.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
@@ -143,7 +151,7 @@ def main():
 
     t0 = time.perf_counter()
     S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
-                          precision="mixed", profile=True)
+                          precision="mixed", profile=True, smooth_interval=smooth)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup * 1e3:.1f} ms")
@@ -180,7 +188,9 @@ def main():
         "config": {"workload": sh.name, "grid": [sh.nlon, sh.nlat, sh.nlev],
                    "unknowns": sh.n, "cycle": f"V({sh.nu_pre},{sh.nu_post})",
                    "tol": args.tol, "levels": st.levels, "iters": st.iters,
-                   "precision": "FP32 V-cycle inside FP64 refinement"},
+                   "precision": "FP32 V-cycle inside FP64 refinement",
+                   "smoothing": (f"Chebyshev factors on [{smooth[0]:g}, {smooth[1]:g}]"
+                                 if smooth else "omega 0.8 every sweep")},
         "median_s": statistics.median(times),
         "relres": st.relres,
         "setup_s": t_setup,
@@ -202,7 +212,7 @@ def main():
 
     if not args.no_fp64:
         S64 = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
-                                precision="fp64", profile=True)
+                                precision="fp64", profile=True, smooth_interval=smooth)
         times64, stats64, total64 = run(S64, args.steps, args.warmup, "fp64")
         d = (u - u_mixed).norm() / u.norm()
         out["fp64_solve_s"] = total64 / args.steps
@@ -212,7 +222,7 @@ def main():
         S64.close()
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sh, st.iters)
+        out["cpu_baseline"] = cpu_baseline(sh, st.iters, smooth)
     print(json.dumps(out), flush=True)
 
 

@@ -95,7 +95,17 @@ typedef struct {
  * stream        : hipStream_t used for all work (NULL = default stream).
  * profile       : 0 = off; 1 = time every finest-level kernel launch with
  *                 HIP events and report per-kernel totals in mg_stats;
- *                 2 = time every launch on every level (adds small gaps). */
+ *                 2 = time every launch on every level (adds small gaps).
+ * smooth_lo, smooth_hi: smoothing interval. smooth_lo > 0 (default 1/3,
+ *                 2): the nu sweeps of one smoothing step use damping
+ *                 factors omega_k = 1/lambda_k, k = 0..nu-1, with lambda_k
+ *                 the nu Chebyshev nodes of [smooth_lo, smooth_hi] (the
+ *                 eigenvalues of H_z^{-1} H the smoother must damp), in
+ *                 decreasing order of lambda; 0 < smooth_lo < smooth_hi.
+ *                 For V(2,2) on [1/3, 2] these are 0.570 and 1.732.
+ *                 smooth_lo = 0: every pre- and post-smoothing sweep uses
+ *                 omega. A smoothing step of one sweep (nu = 1) and the
+ *                 coarsest-level sweeps always use omega. */
 typedef struct {
     int32_t levels;
     int32_t nu_pre, nu_post, coarse_sweeps, max_iters;
@@ -103,6 +113,7 @@ typedef struct {
     int32_t precision;
     void* stream;
     int32_t profile;
+    double smooth_lo, smooth_hi;
 } mg_options;
 
 /* Kernel classes reported by mg_stats when profiling. */
@@ -149,7 +160,9 @@ typedef struct mg_handle mg_handle;
 
 /* Fill *opts with defaults: levels 0 (auto), V(2,2), 20 coarse sweeps,
  * max_iters 100, omega 0.8, semi_threshold 2, MG_PREC_MIXED, default stream,
- * no profiling. */
+ * no profiling, smoothing interval [1/3, 2] (the eigenvalues of H_z^{-1} H
+ * on the modes the smoother must damp when merged latitude rows carry
+ * anisotropy up to semi_threshold = 2: from 1/(1 + 2) to 2). */
 void mg_options_default(mg_options* opts);
 
 /* Build the hierarchy for grid and coefficients (Sections 2.1-2.3):

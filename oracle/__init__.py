@@ -31,12 +31,12 @@ from .operator import apply, mtilde, assemble, column_pivots, column_solve
 from .multigrid import (Options, sweep, sweep_from_zero, restrict, prolong,
                         prolong_T, inject, prolong_weights,
                         vcycle, vcycle_T, solve, solve_adjoint,
-                        grad_alpha, cell_volumes, convergence_factors)
+                        grad_alpha, cell_volumes, convergence_factors, sweep_omegas)
 
 __all__ = [
     "vertical_coords", "fine_lat_edges", "Level", "build_hierarchy",
     "coarsen_rows", "anisotropy", "apply", "mtilde", "assemble",
     "column_pivots", "column_solve", "Options", "sweep", "sweep_from_zero",
     "restrict", "prolong", "prolong_T", "inject", "prolong_weights", "vcycle", "vcycle_T", "solve", "solve_adjoint",
-    "grad_alpha", "cell_volumes", "convergence_factors",
+    "grad_alpha", "cell_volumes", "convergence_factors", "sweep_omegas",
 ]

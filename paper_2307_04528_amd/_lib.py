@@ -37,7 +37,8 @@ class mg_options(C.Structure):
     _fields_ = [("levels", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("max_iters", C.c_int32),
                 ("omega", C.c_double), ("semi_threshold", C.c_double),
-                ("precision", C.c_int32), ("stream", C.c_void_p), ("profile", C.c_int32)]
+                ("precision", C.c_int32), ("stream", C.c_void_p), ("profile", C.c_int32),
+                ("smooth_lo", C.c_double), ("smooth_hi", C.c_double)]
 
 
 class mg_stats(C.Structure):

@@ -422,7 +422,7 @@ __global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
 __attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
 void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
                 T* xbout,  // may alias xb
-                T* __restrict__ zout, T* __restrict__ fb, T omega, int wpr) {
+                T* __restrict__ zout, T* __restrict__ fb, T omega_prev, T omega, int wpr) {
     constexpr int PB = PairsPerBlock<T>::value;
     __shared__ T xch[PB][256];
     const PairOf p = pair_of_wave();
@@ -430,7 +430,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
     const NbB<T> b(g);
     const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
-    const T keep = T(1) - omega;
+    const T keep = T(1) - omega_prev;
     auto fetch = [&](int, int kk) {
         StencilRaw<T> r{};
         r.f = ldb<T>(layer(xb, kk, Pb), b.c);
@@ -448,7 +448,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
             const T h = tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
                         tab(L.Tth, kk * (nJ + 1) + J) * r.s +
                         tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
-            return keep * r.f + omega * h;
+            return keep * r.f + omega_prev * h;
         }
         return r.f;
     };
@@ -557,15 +557,16 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
 
 template <typename T>
 void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
-                      T* fb, T omega, bool accumulate, hipStream_t s) {
+                      T* fb, T omega_prev, T omega, bool accumulate, hipStream_t s) {
     const int wpr = segments_per_row(L.nI);
     const int nb = pair_blocks<T>(L.nJ, wpr);
     constexpr int threads = 128 * PairsPerBlock<T>::value;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int D = ChunkDepth<T>::value;
-#define MG_SMOOTHT_LAUNCH(HZ, AC) \
-    k_smooth_T<T, NZ, D, HZ, AC><<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega, wpr)
+#define MG_SMOOTHT_LAUNCH(HZ, AC)                                                          \
+    k_smooth_T<T, NZ, D, HZ, AC><<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega_prev, \
+                                                       omega, wpr)
         if (zin) {
             if (accumulate) MG_SMOOTHT_LAUNCH(true, true); else MG_SMOOTHT_LAUNCH(true, false);
         } else {
@@ -593,7 +594,7 @@ bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int swee
     template int coarse_solve<T>(const LevelView<T>&, const T*, T*, T*, T, int, size_t,       \
                                  hipStream_t);                                              \
     template void smooth_transpose<T>(const LevelView<T>&, const T*, const T*, T*, T*, T*, \
-                                      T, bool, hipStream_t);                                \
+                                      T, T, bool, hipStream_t);                             \
     template void adjoint_stencil<T>(const LevelView<T>&, const T*, T*, T, hipStream_t);
 MG_INST(float)
 MG_INST(double)

@@ -109,12 +109,14 @@ template <typename T>
 void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X,
                              const T* fcb, T* xb, T* fb, hipStream_t s);
 
-// One kernel of the transposed smoother chain:
-//   xb' = zin ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout if set)
+// One kernel of the transposed smoother chain (it completes the transposed
+// sweep before it, of factor omega_prev, and starts the next, of factor omega):
+//   xb' = zin ? (1-omega_prev) xb + omega_prev sum_h T_h zin_nb : xb
+//         (-> xbout if set)
 //   z   = H_z^{-1} xb';  fb = (accumulate ? fb : 0) + omega z;  zout = z if set.
 template <typename T>
 void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout,
-                      T* zout, T* fb, T omega, bool accumulate, hipStream_t s);
+                      T* zout, T* fb, T omega_prev, T omega, bool accumulate, hipStream_t s);
 
 // xb = (1-omega) xb + omega sum_h T_h z_nb (in place on xb).
 template <typename T>

@@ -196,7 +196,18 @@ std::string validate(const mg_grid& g, const mg_options& o) {
         return "semi_threshold must be finite and > 0";
     if (o.precision != MG_PREC_MIXED && o.precision != MG_PREC_FP64)
         return "precision must be MG_PREC_MIXED or MG_PREC_FP64";
+    if (o.smooth_lo != 0.0 &&
+        !(o.smooth_lo > 0 && o.smooth_hi > o.smooth_lo && std::isfinite(o.smooth_hi)))
+        return "smoothing interval must be 0 or 0 < smooth_lo < smooth_hi";
     return "";
+}
+
+double sweep_omega(const mg_options& o, int nu, int k) {
+    if (o.smooth_lo == 0.0 || nu < 2) return o.omega;   // one sweep: omega
+    // the k-th Chebyshev node of [lo, hi] (decreasing in k)
+    const double lo = o.smooth_lo, hi = o.smooth_hi, pi = 3.14159265358979323846;
+    const double lam = 0.5 * (hi + lo) + 0.5 * (hi - lo) * std::cos(pi * (2 * k + 1) / (2.0 * nu));
+    return 1.0 / lam;
 }
 
 std::string plan(const mg_grid& g, int levels, double threshold, Hierarchy& H) {

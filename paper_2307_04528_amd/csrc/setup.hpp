@@ -46,6 +46,10 @@ struct Hierarchy {
 // Validate grid and options; returns an empty string or an error message.
 std::string validate(const mg_grid& g, const mg_options& o);
 
+// omega of sweep k (0-based) of a smoothing step of nu sweeps: o.omega, or
+// 1/lambda_k for the Chebyshev nodes lambda_k of [smooth_lo, smooth_hi].
+double sweep_omega(const mg_options& o, int nu, int k);
+
 // Build the hierarchy (tables and maps) for the grid with the given level
 // rule (levels == 0: automatic) and anisotropy threshold.
 std::string plan(const mg_grid& g, int levels, double threshold, Hierarchy& out);

@@ -283,12 +283,13 @@ mg_status check_launch(mg_handle* h, const char* what) {
 
 // --- level operations with byte accounting ---------------------------------------
 template <typename T>
-mg_status op_smooth(mg_handle* h, int l, const T* f, const T* xin, T* xout, int cls) {
+mg_status op_smooth(mg_handle* h, int l, const T* f, const T* xin, T* xout, int cls,
+                    double omega) {
     DevLevel& d = h->lv[l];
     const double bytes = double(d.n) * sizeof(T) * (xin ? 4 : 3);
     {
         Launch g(h, cls, l, bytes);
-        mgk::smooth<T>(view<T>(d), f, xin, xout, T(h->opt.omega), h->stream);
+        mgk::smooth<T>(view<T>(d), f, xin, xout, T(omega), h->stream);
     }
     return check_launch(h, "smooth");
 }
@@ -347,17 +348,18 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
             *result = where == 0 ? cur : nxt;
             return MG_OK;
         }
-        MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_COARSE));
+        MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_COARSE, h->opt.omega));
         for (int s = 1; s < h->opt.coarse_sweeps; ++s) {
-            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_COARSE));
+            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_COARSE, h->opt.omega));
             std::swap(cur, nxt);
         }
         *result = cur;
         return MG_OK;
     }
-    MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH0));
-    for (int s = 1; s < h->opt.nu_pre; ++s) {
-        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH));
+    const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
+    MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH0, mgs::sweep_omega(h->opt, nu1, 0)));
+    for (int s = 1; s < nu1; ++s) {
+        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH, mgs::sweep_omega(h->opt, nu1, s)));
         std::swap(cur, nxt);
     }
     Work<T>& wc = work<T>(h->lv[l + 1]);
@@ -365,32 +367,34 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     T* xc = nullptr;
     MG_TRY(vcycle<T>(h, l + 1, wc.f, &xc));
     MG_TRY(op_prolong<T>(h, l, xc, cur));
-    for (int s = 0; s < h->opt.nu_post; ++s) {
-        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH));
+    for (int s = 0; s < nu2; ++s) {
+        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH, mgs::sweep_omega(h->opt, nu2, s)));
         std::swap(cur, nxt);
     }
     *result = cur;
     return MG_OK;
 }
 
-// Transposed smoother chain of `sweeps` sweeps starting from xbar (no pending
-// column solve). Leaves the last column solve in *zlast (stencil pending) and
-// accumulates fbar. first_sets_fbar: the first kernel writes fbar instead of
-// adding to it.
+// Transposed smoother chain starting from xbar (no pending column solve):
+// the transposed sweeps of factors oms[0], oms[1], ... in that order. Leaves
+// the last column solve in *zlast (its stencil pending) and accumulates fbar.
+// first_sets_fbar: the first kernel writes fbar instead of adding to it.
 template <typename T>
-mg_status chain_T(mg_handle* h, int l, int sweeps, bool first_sets_fbar, T** zlast) {
+mg_status chain_T(mg_handle* h, int l, const std::vector<double>& oms, bool first_sets_fbar,
+                  T** zlast) {
     DevLevel& d = h->lv[l];
     Work<T>& w = work<T>(d);
-    const T om = T(h->opt.omega);
     T* zin = nullptr;
     T* zout = w.za;
+    const int sweeps = int(oms.size());
     for (int s = 0; s < sweeps; ++s) {
         const bool acc = !(first_sets_fbar && s == 0);
         const double bytes = double(d.n) * sizeof(T) * (zin ? 6 : 4);
         {
             Launch g(h, MG_K_ADJOINT, l, bytes);
             mgk::smooth_transpose<T>(view<T>(d), w.xbar, zin, zin ? w.xbar : nullptr, zout,
-                                     w.fbar, om, acc, h->stream);
+                                     w.fbar, T(s > 0 ? oms[s - 1] : oms[0]), T(oms[s]), acc,
+                                     h->stream);
         }
         MG_TRY(check_launch(h, "smooth_transpose"));
         zin = zout;
@@ -407,7 +411,7 @@ mg_status vcycle_T(mg_handle* h, int l) {
     DevLevel& d = h->lv[l];
     Work<T>& w = work<T>(d);
     const int last = int(h->lv.size()) - 1;
-    const T om = T(h->opt.omega);
+    const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
     T* z = nullptr;
     if (l == last) {
         if (h->dense.valid) {
@@ -420,14 +424,17 @@ mg_status vcycle_T(mg_handle* h, int l) {
         }
         // (coarse_sweeps - 1) transposed sweeps, then the transposed first
         // sweep: fbar += omega H_z^{-1} xbar, all as one chain
-        return chain_T<T>(h, l, h->opt.coarse_sweeps, true, &z);
+        return chain_T<T>(h, l, std::vector<double>(h->opt.coarse_sweeps, h->opt.omega), true,
+                          &z);
     }
-    // post-sweeps
-    if (h->opt.nu_post > 0) {
-        MG_TRY(chain_T<T>(h, l, h->opt.nu_post, true, &z));
+    // post-sweeps, last first
+    if (nu2 > 0) {
+        std::vector<double> oms;
+        for (int s = nu2 - 1; s >= 0; --s) oms.push_back(mgs::sweep_omega(h->opt, nu2, s));
+        MG_TRY(chain_T<T>(h, l, oms, true, &z));
         {
             Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) * 3);
-            mgk::adjoint_stencil<T>(view<T>(d), z, w.xbar, om, h->stream);
+            mgk::adjoint_stencil<T>(view<T>(d), z, w.xbar, T(oms.back()), h->stream);
         }
         MG_TRY(check_launch(h, "adjoint_stencil"));
     } else {
@@ -447,8 +454,10 @@ mg_status vcycle_T(mg_handle* h, int l) {
                                         h->stream);
     }
     MG_TRY(check_launch(h, "inject_residual_adjoint"));
-    // (nu_pre - 1) transposed pre-sweeps and the transposed first sweep
-    return chain_T<T>(h, l, h->opt.nu_pre, false, &z);
+    // the transposed pre-sweeps, last first, ending with the first sweep
+    std::vector<double> oms;
+    for (int s = nu1 - 1; s >= 0; --s) oms.push_back(mgs::sweep_omega(h->opt, nu1, s));
+    return chain_T<T>(h, l, oms, false, &z);
 }
 
 mg_status sync_scalar(mg_handle* h, double* out) {
@@ -713,7 +722,7 @@ mg_status level_sweep(mg_handle* h, int l, const double* f, const double* xin, d
     to_level<T>(h, f, w.f, d.n);
     if (xin) to_level<T>(h, xin, w.xa, d.n);
     MG_TRY(op_smooth<T>(h, l, w.f, xin ? w.xa : nullptr, w.xb,
-                        xin ? MG_K_SMOOTH : MG_K_SMOOTH0));
+                        xin ? MG_K_SMOOTH : MG_K_SMOOTH0, h->opt.omega));
     from_level<T>(h, w.xb, xout, d.n);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return check_launch(h, "level_sweep");
@@ -784,6 +793,8 @@ void mg_options_default(mg_options* o) {
     o->precision = MG_PREC_MIXED;
     o->stream = nullptr;
     o->profile = 0;
+    o->smooth_lo = 1.0 / 3.0;
+    o->smooth_hi = 2.0;
 }
 
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,

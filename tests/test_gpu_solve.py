@@ -229,3 +229,26 @@ def test_autograd_finite_differences_small():
         assert fd_b == pytest.approx(an_b, rel=1e-6)
         assert fd_a == pytest.approx(an_a, rel=1e-6)
     del torch
+
+
+@pytest.mark.parametrize("nu", [(2, 2), (2, 1)])
+def test_vcycle_chebyshev_smoothing(nu):
+    """Per-sweep damping factors from the Chebyshev nodes of [1/3, 2]: the
+    forward and transposed V-cycles against the oracle's, and a solve."""
+    sh = DEEP
+    a, f = shellgen.alpha(sh), shellgen.rhs(sh)
+    S = solver_for(sh, a, precision="fp64", nu_pre=nu[0], nu_post=nu[1],
+                   smooth_interval=(1 / 3, 2.0))
+    L = hierarchy(sh)
+    opt = opts_of(sh, nu_pre=nu[0], nu_post=nu[1], smooth_lo=1 / 3, smooth_hi=2.0)
+    got, gotT = n(S.vcycle(t(f))), n(S.vcycle(t(f), transposed=True))
+    ref, refT = oracle.vcycle(L, f, opt), oracle.vcycle_T(L, f, opt)
+    log(f"chebyshev vcycle {nu}: {rel_inf(got, ref):.2e} transposed {rel_inf(gotT, refT):.2e}")
+    assert rel_inf(got, ref) < 1e-12
+    assert rel_inf(gotT, refT) < 1e-12
+    if nu == (2, 2):
+        M = solver_for(sh, a, precision="mixed", smooth_interval=(1 / 3, 2.0))
+        u, st = M.solve(t(f), tol=1e-11)
+        u_ref, _ = oracle_solution(sh)
+        log(f"chebyshev mixed solve: {st.iters} iterations, fwd err {rel2(n(u), u_ref):.2e}")
+        assert st.relres <= 1e-11 and rel2(n(u), u_ref) < 1e-8

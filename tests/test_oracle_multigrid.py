@@ -169,3 +169,53 @@ def test_adjoint_matches_direct_and_finite_differences():
         assert fd_b == pytest.approx(np.vdot(lam, d), rel=1e-7)
         fd_a = (loss(a * (1 + h * d), b) - loss(a * (1 - h * d), b)) / (2 * h)
         assert fd_a == pytest.approx(np.vdot(g, a * d), rel=1e-6)
+
+
+def test_chebyshev_sweep_factors_closed_form():
+    """With a smoothing interval [lo, hi] the nu sweeps of one smoothing step
+    multiply an eigencomponent lambda of H_z^{-1} H by prod_k (1 - w_k
+    lambda), which must be the Chebyshev polynomial of degree nu on [lo, hi],
+    scaled to 1 at lambda = 0 (closed form T_nu(z) = cos(nu arccos z) inside
+    the interval, cosh(nu arccosh z) outside)."""
+    from oracle import sweep_omegas
+    lo, hi = 1.0 / 3.0, 2.0
+    opt = Options(smooth_lo=lo, smooth_hi=hi)
+    # a single sweep keeps omega
+    assert sweep_omegas(opt, 1) == [opt.omega]
+    for nu in (2, 3, 4):
+        w = np.array(sweep_omegas(opt, nu))
+        lam = np.linspace(0.0, 2.5, 101)
+        got = np.prod(1.0 - np.outer(lam, w), axis=1)
+        z = (hi + lo - 2.0 * lam) / (hi - lo)
+        t_nu = np.where(np.abs(z) <= 1, np.cos(nu * np.arccos(np.clip(z, -1, 1))),
+                        np.sign(z) ** nu * np.cosh(nu * np.arccosh(np.maximum(np.abs(z), 1))))
+        z0 = (hi + lo) / (hi - lo)
+        want = t_nu / np.cosh(nu * np.arccosh(z0))
+        np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-13)
+    # largest eigenvalue node first: the smallest factor leads
+    assert np.all(np.diff(sweep_omegas(opt, 3)) > 0)
+    # no interval: every sweep uses omega
+    assert sweep_omegas(Options(omega=0.7, smooth_lo=0.0), 3) == [0.7, 0.7, 0.7]
+
+
+@pytest.mark.parametrize("nu", [(2, 2), (2, 1)])
+def test_chebyshev_vcycle_transpose_and_convergence(nu):
+    sh, L = _setup(32, 16, 5, q=1.2)
+    opt = Options(nu_pre=nu[0], nu_post=nu[1], coarse_sweeps=4, smooth_lo=1 / 3, smooth_hi=2.0)
+    rng = np.random.default_rng(19)
+    x, y = rng.standard_normal(sh.shape), rng.standard_normal(sh.shape)
+    assert np.vdot(vcycle(L, x, opt), y) == pytest.approx(np.vdot(x, vcycle_T(L, y, opt)),
+                                                          rel=1e-12)
+    if nu == (2, 2):
+        # the schedule damps the smoothing range better than a constant
+        # factor: smaller convergence factors once the first, white-noise
+        # dominated iteration is past
+        sh2 = shellgen.workload("shell384x192x70").with_(nlon=192, nlat=96)
+        L2 = build_hierarchy(sh2, shellgen.alpha(sh2))
+        b = shellgen.rhs(sh2)
+        _, st_c = solve(L2, b, Options(smooth_lo=0.0), tol=1e-11, fixed_iters=6)
+        _, st_t = solve(L2, b, Options(smooth_lo=1 / 3, smooth_hi=2.0), tol=1e-11,
+                        fixed_iters=6)
+        rho_c = convergence_factors(st_c["res_hist"])[-3:]
+        rho_t = convergence_factors(st_t["res_hist"])[-3:]
+        assert rho_t.max() < 0.12 and rho_t.max() < 0.8 * rho_c.min(), (rho_c, rho_t)
