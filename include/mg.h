@@ -158,7 +158,7 @@ typedef struct {
 
 typedef struct mg_handle mg_handle;
 
-/* Fill *opts with defaults: levels 0 (auto), V(2,2), 20 coarse sweeps,
+/* Fill *opts with defaults: levels 0 (auto), V(2,2), 40 coarse sweeps,
  * max_iters 100, omega 0.8, semi_threshold 2, MG_PREC_MIXED, default stream,
  * no profiling, smoothing interval [1/3, 2] (the eigenvalues of H_z^{-1} H
  * on the modes the smoother must damp when merged latitude rows carry

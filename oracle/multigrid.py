@@ -14,10 +14,13 @@ Paper steps followed:
     correction and smooths again. Each outer iteration should reduce the
     residual norm ||b - Hu|| by about an order of magnitude.
   * Section 2.3: the coarsest grid is handled by "a simple iterative method";
-    here n_c smoother sweeps from zero (n_c = 20 by default: on the
-    1024x768x70 shell 10 sweeps leave the coarse error large enough to raise
-    the V-cycle's convergence factor from about 0.27 to 0.45, while 40 sweeps
-    do no better than 20).
+    here n_c smoother sweeps (with the factor omega) from zero, n_c = 40 by
+    default. Fewer leave enough coarse error to dominate the convergence
+    factor once the smoother is good: with the Chebyshev factors below, 20
+    sweeps let the factor climb from about 0.1 to 0.26 (1024x768x70 shell)
+    and 0.48 (2560x1920x70, whose coarsest level stops at 5 longitudes,
+    still anisotropic) after a few iterations, 40 keep it at or below 0.13
+    on both, and 80 or 160 do no better.
 
 Readings where the paper is silent:
   * restriction R sums the residuals of the children cells (the residual is
@@ -62,7 +65,7 @@ class Options:
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 0.8
-    coarse_sweeps: int = 20
+    coarse_sweeps: int = 40
     max_iters: int = 100
     # the interval [lo, hi] of the Chebyshev smoothing factors (see
     # sweep_omegas); lo = 0: every smoothing sweep uses omega

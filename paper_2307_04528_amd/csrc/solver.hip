@@ -786,7 +786,7 @@ void mg_options_default(mg_options* o) {
     o->levels = 0;
     o->nu_pre = 2;
     o->nu_post = 2;
-    o->coarse_sweeps = 20;
+    o->coarse_sweeps = 40;
     o->max_iters = 100;
     o->omega = 0.8;
     o->semi_threshold = 2.0;

@@ -43,7 +43,7 @@ def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
                      float(stretch), float(K))
 
 
-def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=20, max_iters=100, omega=0.8,
+def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, omega=0.8,
              semi_threshold=2.0, precision="mixed", profile=False, stream=None,
              smooth_interval=(1.0 / 3.0, 2.0)) -> L.mg_options:
     """smooth_interval: (lo, hi), per-sweep omegas from the Chebyshev nodes of

@@ -104,7 +104,7 @@ def test_coarse_matrix_follows_options_and_coefficients():
     S = solver_for(sh, a, precision="fp64")
     L = hierarchy(sh)
     f = shellgen.rhs(sh)
-    for nc, om in [(7, 0.8), (7, 0.7), (20, 0.8)]:
+    for nc, om in [(7, 0.8), (7, 0.7), (40, 0.8)]:
         S.set_options(coarse_sweeps=nc, omega=om)
         got = n(S.vcycle(t(f)))
         ref = oracle.vcycle(L, f, opts_of(sh, coarse_sweeps=nc, omega=om))
