@@ -105,7 +105,12 @@ typedef struct {
  *                 For V(2,2) on [1/3, 2] these are 0.570 and 1.732.
  *                 smooth_lo = 0: every pre- and post-smoothing sweep uses
  *                 omega. A smoothing step of one sweep (nu = 1) and the
- *                 coarsest-level sweeps always use omega. */
+ *                 coarsest-level sweeps always use omega.
+ * staged_columns: levels with fewer columns (nlon * nlat) than this run
+ *                 their sweeps with the staged kernel: eight wavefronts
+ *                 load a 64-column segment into LDS in one round trip, two
+ *                 solve its columns from there (default 65536; 0 = never).
+ *                 Same arithmetic either way; only the speed differs. */
 typedef struct {
     int32_t levels;
     int32_t nu_pre, nu_post, coarse_sweeps, max_iters;
@@ -114,6 +119,7 @@ typedef struct {
     void* stream;
     int32_t profile;
     double smooth_lo, smooth_hi;
+    int32_t staged_columns;
 } mg_options;
 
 /* Kernel classes reported by mg_stats when profiling. */

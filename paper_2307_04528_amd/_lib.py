@@ -38,7 +38,8 @@ class mg_options(C.Structure):
                 ("coarse_sweeps", C.c_int32), ("max_iters", C.c_int32),
                 ("omega", C.c_double), ("semi_threshold", C.c_double),
                 ("precision", C.c_int32), ("stream", C.c_void_p), ("profile", C.c_int32),
-                ("smooth_lo", C.c_double), ("smooth_hi", C.c_double)]
+                ("smooth_lo", C.c_double), ("smooth_hi", C.c_double),
+                ("staged_columns", C.c_int32)]
 
 
 class mg_stats(C.Structure):

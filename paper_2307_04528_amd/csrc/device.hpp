@@ -163,6 +163,53 @@ __device__ __forceinline__ T tab(const T* p, int idx) {
     return ((const __attribute__((address_space(4))) T*)p)[idx];
 }
 
+// The value of x in lane l (l wave-uniform).
+__device__ __forceinline__ float lane_value(float x, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double lane_value(double x, int l) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+    const unsigned lo = unsigned(__builtin_amdgcn_readlane(int(unsigned(u)), l));
+    const unsigned hi = unsigned(__builtin_amdgcn_readlane(int(unsigned(u >> 32)), l));
+    return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// One latitude row J of a coefficient table, tab[F * stride + J] for
+// F = 0..count-1 (count <= N), spread over the lanes of a wavefront (lane l
+// of slot r holds entry 64 r + l) and read back with readlane at a
+// wave-uniform index. A column recurrence that reads its couplings this way
+// waits on no memory access per layer; through tab() each layer's couplings
+// are scalar loads, and every step waits for one.
+template <typename T, int N>
+struct LaneTable {
+    static constexpr int R = (N + 63) / 64;
+    T v[R];
+    __device__ __forceinline__ LaneTable(const T* tab, int stride, int J, int count) {
+        const int lane = int(threadIdx.x & 63u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int F = r * 64 + lane;
+            v[r] = F < count ? tab[size_t(F) * size_t(stride) + size_t(J)] : T(0);
+        }
+    }
+    __device__ __forceinline__ T operator()(int F) const {
+        const int l = F & 63, r = F >> 6;
+        T x = lane_value(v[0], l);
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+            const T y = lane_value(v[q], l);
+            x = (r == q) ? y : x;
+        }
+        return x;
+    }
+};
+
+// Stands in for a LaneTable where the table is read through tab() instead.
+template <typename T>
+struct NoLaneTable {
+    __device__ __forceinline__ NoLaneTable(const T*, int, int, int) {}
+};
+
 template <typename T>
 __device__ __forceinline__ void block_sum_to(T v, T* out) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

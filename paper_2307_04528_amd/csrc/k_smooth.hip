@@ -51,6 +51,12 @@ namespace mgk {
 #ifndef MG_RAW64
 #define MG_RAW64 1
 #endif
+#ifndef MG_LANE_TABLES32
+#define MG_LANE_TABLES32 1
+#endif
+#ifndef MG_LANE_TABLES64
+#define MG_LANE_TABLES64 0
+#endif
 
 namespace {
 using namespace dev;
@@ -84,6 +90,14 @@ template <typename T>
 struct RawPrefetch {
     static constexpr bool value = std::is_same<T, float>::value ? (MG_RAW32 != 0)
                                                                 : (MG_RAW64 != 0);
+};
+
+// Read a wavefront's row couplings from lane tables (FP32) or with scalar
+// loads (FP64: the tables' registers would spill the x sweep).
+template <typename T>
+struct LaneTables {
+    static constexpr bool value = std::is_same<T, float>::value ? (MG_LANE_TABLES32 != 0)
+                                                                : (MG_LANE_TABLES64 != 0);
 };
 
 // Steps of one wavefront of a pair for the layer bucket NZ.
@@ -249,17 +263,32 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
         }
         return r;
     };
+    // couplings of the row from lane tables (no memory wait per layer), or
+    // through scalar loads where the registers are not there (FP64)
+    constexpr bool LT = LaneTables<T>::value;
+    using TabH = std::conditional_t<LT, LaneTable<T, NZ>, NoLaneTable<T>>;
+    using TabV = std::conditional_t<LT, LaneTable<T, NZ + 1>, NoLaneTable<T>>;
+    const int nzl = HAS_X ? L.nz : 0;
+    const TabH tl(L.Tlam, nJ, J, nzl), ts(L.Tth, nJ + 1, J, nzl), tn(L.Tth, nJ + 1, J + 1, nzl);
+    const TabV tr(L.Tr, nJ, J, L.nz + 1);
     auto comb = [&](int t, int kk, const StencilRaw<T>& r) -> T {
         T s = r.f;
         if constexpr (HAS_X) {
-            s += tab(L.Tlam, kk * nJ + J) * (r.w + r.e) + tab(L.Tth, kk * (nJ + 1) + J) * r.s +
-                 tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
+            if constexpr (LT)
+                s += tl(kk) * (r.w + r.e) + ts(kk) * r.s + tn(kk) * r.n;
+            else
+                s += tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
+                     tab(L.Tth, kk * (nJ + 1) + J) * r.s +
+                     tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
             if constexpr (KX) xk[t] = r.c;
         }
         return s;
     };
+    auto cpl = [&](int F) -> T {
+        if constexpr (LT) return tr(F);
+        else return tab(L.Tr, F * nJ + J);
+    };
     auto inv = [&](int kk) -> T { return ldb<T>(layer(L.invp, kk, Pb), b.c); };
-    auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
     auto fsink = [](int, int, T) {};
     auto bload = [&](int kk) -> T { return ldb<T>(layer(xin, kk, Pb), b.c); };
     auto sink = [&](int t, int kk, T z, T e) {
@@ -295,6 +324,153 @@ void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin
     const PairOf p = pair_of_wave();
     const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
     sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
+}
+
+// ---------------------------------------------------------------------------
+// Staged sweep for small levels. A level of a few thousand columns leaves
+// most of the GPU idle: a sweep then costs the critical path of one column
+// (its memory round trips and the instructions of its recurrences), not
+// bandwidth. Here kStageWaves wavefronts share one segment of 64 columns:
+// wavefront w loads layers w, w + kStageWaves, ... (all of its loads in one
+// round trip), forms the right-hand sides s = f + sum_h T_h x_nb and writes
+// s, the inverse pivots, the old iterate and the row's couplings Tr to LDS.
+// After one block barrier the first two wavefronts solve the twisted
+// factorisation of H_z in rolled loops over LDS (no per-layer address or
+// branch arithmetic of a fully unrolled register solve), with the same
+// arithmetic in the same order as k_smooth: the forward values y_k overwrite
+// s_k, the couplings Tr_next * ip_k overwrite the pivots.
+constexpr int kStageWaves = 8;
+
+// Dynamic LDS of k_smooth_staged (its static LDS holds NZ + 8 + 256 values).
+template <typename T, int NZ, bool HAS_X>
+constexpr size_t staged_lds_bytes() {
+    return sizeof(T) * size_t(HAS_X ? 3 : 2) * NZ * 64;
+}
+
+template <typename T, int NZ, bool HAS_X>
+__global__ __launch_bounds__(64 * kStageWaves) void k_smooth_staged(
+    LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin, T* __restrict__ xout,
+    T omega, int wpr) {
+    extern __shared__ unsigned char smem_raw[];
+    T* ls = reinterpret_cast<T*>(smem_raw);   // [NZ][64] s_k, then y_k
+    T* lp = ls + NZ * 64;                      // [NZ][64] ip_k, then cb_k
+    T* lx = lp + NZ * 64;                      // [NZ][64] old iterate (HAS_X)
+    // separate LDS objects: the compiler then knows that the column loops'
+    // stores to ls and lp leave the couplings alone
+    __shared__ T ltr[NZ + 8];   // Tr_F of the row
+    __shared__ T xch[256];      // the pair's exchange
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int lane = int(threadIdx.x & 63u);
+    const Seg g = segment(int(blockIdx.x), L.nI, L.nJ, wpr);
+    const NbB<T> b(g);
+    const int nz = L.nz, nJ = L.nJ, J = g.J;
+    const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
+    constexpr int Q = (NZ + kStageWaves - 1) / kStageWaves;
+    {
+        const int F = int(threadIdx.x);
+        const T trF = F <= nz ? L.Tr[size_t(F) * size_t(nJ) + size_t(J)] : T(0);
+        // the horizontal couplings of this wavefront's layers: lane q holds
+        // those of layer wave + q kStageWaves (vector loads issued with the
+        // stencil loads, read back with readlane)
+        T ctl = T(0), cts = T(0), ctn = T(0);
+        if (HAS_X && lane < Q) {
+            const int kq = clampk(wave + lane * kStageWaves, nz);
+            ctl = L.Tlam[size_t(kq) * size_t(nJ) + size_t(J)];
+            cts = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J)];
+            ctn = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J) + 1];
+        }
+        T rf[Q], rp[Q], rc[HAS_X ? Q : 1], rw[HAS_X ? Q : 1], re[HAS_X ? Q : 1],
+            rs[HAS_X ? Q : 1], rn[HAS_X ? Q : 1];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int kk = clampk(wave + q * kStageWaves, nz);
+            rf[q] = ldb<T>(layer(f, kk, Pb), b.c);
+            rp[q] = ldb<T>(layer(L.invp, kk, Pb), b.c);
+            if constexpr (HAS_X) {
+                gcptr xl = layer(xin, kk, Pb);
+                rc[q] = ldb<T>(xl, b.c);
+                rw[q] = ldb<T>(xl, b.w);
+                re[q] = ldb<T>(xl, b.e);
+                rs[q] = ldb<T>(xl, b.s);
+                rn[q] = ldb<T>(xl, b.n);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (F <= nz) ltr[F] = trF;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = wave + q * kStageWaves;
+            if (k < nz) {
+                T s = rf[q];
+                if constexpr (HAS_X) {
+                    s += lane_value(ctl, q) * (rw[q] + re[q]) + lane_value(cts, q) * rs[q] +
+                         lane_value(ctn, q) * rn[q];
+                    lx[k * 64 + lane] = rc[q];
+                }
+                ls[k * 64 + lane] = s;
+                lp[k * 64 + lane] = rp[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (wave >= 2) {
+        __syncthreads();   // the solving pair's exchange barrier
+        return;
+    }
+    const bool top = wave == 1;
+    const int m = nz >> 1;
+    const T keep = T(1) - omega;
+    // forward: bottom eliminates layers 0..m-1 upward, top nz-1..m+1 downward
+    T vp = T(0), sm = T(0), im = T(0);
+    if (!top) {
+#pragma unroll 4
+        for (int k = 0; k < m; ++k) {
+            const T s = ls[k * 64 + lane], ip = lp[k * 64 + lane];
+            const T v = (s + ltr[k] * vp) * ip;
+            ls[k * 64 + lane] = v;
+            lp[k * 64 + lane] = ltr[k + 1] * ip;
+            vp = v;
+        }
+        xch[lane] = vp;
+    } else {
+#pragma unroll 4
+        for (int k = nz - 1; k > m; --k) {
+            const T s = ls[k * 64 + lane], ip = lp[k * 64 + lane];
+            const T v = (s + ltr[k + 1] * vp) * ip;
+            ls[k * 64 + lane] = v;
+            lp[k * 64 + lane] = ltr[k] * ip;
+            vp = v;
+        }
+        sm = ls[m * 64 + lane];
+        im = lp[m * 64 + lane];
+        xch[64 + lane] = vp;
+        xch[128 + lane] = sm;
+        xch[192 + lane] = im;
+    }
+    __syncthreads();
+    // meeting layer: x_m = (s_m + Tr_m y_{m-1} + Tr_{m+1} z_{m+1}) / d_m
+    const T xm =
+        (xch[128 + lane] + ltr[m] * xch[lane] + ltr[m + 1] * xch[64 + lane]) * xch[192 + lane];
+    auto put = [&](int k, T z) {
+        T out = omega * z;
+        if constexpr (HAS_X) out += keep * lx[k * 64 + lane];
+        if (g.valid) stb<T>(layer_w(xout, k, Pb), b.c, out);
+    };
+    T xv = xm;
+    if (!top) {
+#pragma unroll 4
+        for (int k = m - 1; k >= 0; --k) {
+            xv = ls[k * 64 + lane] + lp[k * 64 + lane] * xv;
+            put(k, xv);
+        }
+    } else {
+        put(m, xm);
+#pragma unroll 4
+        for (int k = m + 1; k < nz; ++k) {
+            xv = ls[k * 64 + lane] + lp[k * 64 + lane] * xv;
+            put(k, xv);
+        }
+    }
 }
 
 // The coarsest level in one launch from global memory: one block does every
@@ -498,8 +674,46 @@ inline int pair_blocks(const int nJ, const int wpr) {
 
 }  // namespace
 
+constexpr size_t kMaxLds = 160 * 1024;
+
+// The staged sweep of a small level; false where the level is not small or
+// the staging buffers do not fit in LDS.
 template <typename T>
-void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, hipStream_t s) {
+bool launch_staged(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
+                   long long staged_columns, hipStream_t s) {
+    if (L.plane >= staged_columns) return false;
+    const int wpr = segments_per_row(L.nI);
+    const int nb = L.nJ * wpr;
+    bool launched = false;
+    with_nz(L.nz, [&](auto nzc) {
+        constexpr int NZ = decltype(nzc)::value;
+        auto go = [&](auto hx) {
+            constexpr bool HX = decltype(hx)::value;
+            constexpr size_t lds = staged_lds_bytes<T, NZ, HX>();
+            if constexpr (lds + sizeof(T) * (NZ + 8 + 256) <= kMaxLds) {
+                const void* fn =
+                    reinterpret_cast<const void*>(&k_smooth_staged<T, NZ, HX>);
+                if (lds > 64 * 1024 &&
+                    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(lds)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return;
+                }
+                k_smooth_staged<T, NZ, HX>
+                    <<<nb, 64 * kStageWaves, lds, s>>>(L, f, xin, xout, omega, wpr);
+                launched = true;
+            }
+        };
+        if (xin) go(std::true_type{});
+        else go(std::false_type{});
+    });
+    return launched;
+}
+
+template <typename T>
+void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
+            long long staged_columns, hipStream_t s) {
+    if (launch_staged<T>(L, f, xin, xout, omega, staged_columns, s)) return;
     const int wpr = segments_per_row(L.nI);
     const int nb = pair_blocks<T>(L.nJ, wpr);
     constexpr int threads = 128 * PairsPerBlock<T>::value;
@@ -590,7 +804,8 @@ bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int swee
 }
 
 #define MG_INST(T)                                                                          \
-    template void smooth<T>(const LevelView<T>&, const T*, const T*, T*, T, hipStream_t);   \
+    template void smooth<T>(const LevelView<T>&, const T*, const T*, T*, T, long long,      \
+                            hipStream_t);                                                   \
     template int coarse_solve<T>(const LevelView<T>&, const T*, T*, T*, T, int, size_t,       \
                                  hipStream_t);                                              \
     template void smooth_transpose<T>(const LevelView<T>&, const T*, const T*, T*, T*, T*, \

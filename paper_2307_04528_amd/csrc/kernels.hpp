@@ -45,9 +45,10 @@ void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s);
 // One damped block-Jacobi sweep (Eq. 1):
 //   xout = (1-omega) xin + omega H_z^{-1}(f + sum_h T_h xin_nb),
 // or the sweep from zero xout = omega H_z^{-1} f when xin == nullptr.
+// Levels with fewer than staged_columns columns use the staged kernel.
 template <typename T>
 void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
-            hipStream_t s);
+            long long staged_columns, hipStream_t s);
 
 // The whole coarsest-level solve in one launch (one block): `sweeps` sweeps
 // from zero, ping-ponging between xa and xb. Returns 0 if the result is in

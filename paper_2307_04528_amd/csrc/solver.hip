@@ -289,7 +289,7 @@ mg_status op_smooth(mg_handle* h, int l, const T* f, const T* xin, T* xout, int 
     const double bytes = double(d.n) * sizeof(T) * (xin ? 4 : 3);
     {
         Launch g(h, cls, l, bytes);
-        mgk::smooth<T>(view<T>(d), f, xin, xout, T(omega), h->stream);
+        mgk::smooth<T>(view<T>(d), f, xin, xout, T(omega), h->opt.staged_columns, h->stream);
     }
     return check_launch(h, "smooth");
 }
@@ -795,6 +795,7 @@ void mg_options_default(mg_options* o) {
     o->profile = 0;
     o->smooth_lo = 1.0 / 3.0;
     o->smooth_hi = 2.0;
+    o->staged_columns = 65536;
 }
 
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,

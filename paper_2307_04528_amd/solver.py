@@ -45,10 +45,11 @@ def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
 
 def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, omega=0.8,
              semi_threshold=2.0, precision="mixed", profile=False, stream=None,
-             smooth_interval=(1.0 / 3.0, 2.0)) -> L.mg_options:
+             smooth_interval=(1.0 / 3.0, 2.0), staged_columns=65536) -> L.mg_options:
     """smooth_interval: (lo, hi), per-sweep omegas from the Chebyshev nodes of
     [lo, hi] (the default, see mg.h), or None: every smoothing sweep uses
-    omega."""
+    omega. staged_columns: levels with fewer columns sweep with the staged
+    kernel (0: never)."""
     o = L.mg_options()
     L.lib().mg_options_default(C.byref(o))
     o.levels = int(levels)
@@ -62,6 +63,7 @@ def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, ome
         o.smooth_lo = o.smooth_hi = 0.0
     else:
         o.smooth_lo, o.smooth_hi = float(smooth_interval[0]), float(smooth_interval[1])
+    o.staged_columns = int(staged_columns)
     return o
 
 

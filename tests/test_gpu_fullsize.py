@@ -4,7 +4,8 @@ entry points and launch configuration that bench.py times.
   * shell1024x768x70 (55M cells): one FP32 and one FP64 V-cycle against the
     oracle's, element by element over the whole field; one finest-level
     sweep from an iterate (the benchmark's dominant kernel) and one from
-    zero against the oracle's; the mixed solve to relative residual 1e-8,
+    zero against the oracle's; both sweeps on every coarser level, with and
+    without the staged kernel; the mixed solve to relative residual 1e-8,
     with ||b - H u|| / ||b|| of the returned u recomputed by the oracle on
     the host.
   * shell2560x1920x70 (344M cells): the mixed solve to 1e-8, its residual
@@ -63,6 +64,36 @@ def test_bench_finest_sweeps_full_field():
         f"from an iterate {rel_inf(got, ref):.2e}")
     assert rel_inf(got0, ref0) < 2e-5
     assert rel_inf(got, ref) < 2e-5
+    S.close()
+
+
+@functools.lru_cache(maxsize=None)
+def coarser_sweep_case(l):
+    lev = bench_levels()[l]
+    rng = np.random.default_rng(100 + l)
+    f = rng.uniform(-1, 1, lev.shape)
+    x = rng.uniform(-1, 1, lev.shape)
+    return f, x, oracle.sweep_from_zero(lev, f, 0.8), oracle.sweep(lev, x, f, 0.8)
+
+
+@pytest.mark.parametrize("staged", [True, False], ids=["staged", "pairs"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_coarser_level_sweeps(prec, staged):
+    """The sweeps of every coarser level of the benchmark hierarchy (the
+    largest has 512x504 columns), with the staged kernel on every level or
+    on none, against the oracle's."""
+    L = bench_levels()
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec,
+                   staged_columns=(1 << 30) if staged else 0)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for l in range(1, len(L)):
+        f, x, ref0, ref = coarser_sweep_case(l)
+        got0 = n(S.level_sweep(l, t(f)))
+        got = n(S.level_sweep(l, t(f), t(x)))
+        log(f"level {l} {L[l].shape} {prec} staged={staged}: from zero "
+            f"{rel_inf(got0, ref0):.2e}, from an iterate {rel_inf(got, ref):.2e}")
+        assert rel_inf(got0, ref0) < tol
+        assert rel_inf(got, ref) < tol
     S.close()
 
 

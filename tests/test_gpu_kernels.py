@@ -43,11 +43,15 @@ def test_apply_fp64(sh):
     np.testing.assert_allclose(V, np.broadcast_to(L[0].V[:, :, None], sh.shape), rtol=1e-11)
 
 
+# staged: every level's sweeps with the staged kernel (a segment's loads
+# staged in LDS by eight wavefronts, its columns solved from there), or none
+# (a wavefront pair per segment, straight from memory).
+@pytest.mark.parametrize("staged", [True, False], ids=["staged", "pairs"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("sh", SHELLS, ids=IDS)
-def test_level_kernels(sh, prec):
+def test_level_kernels(sh, prec, staged):
     a = shellgen.alpha(sh)
-    S = solver_for(sh, a, precision=prec)
+    S = solver_for(sh, a, precision=prec, staged_columns=(1 << 30) if staged else 0)
     L = oracle.build_hierarchy(sh, a)
     rng = np.random.default_rng(12)
     tol = TOL[prec]

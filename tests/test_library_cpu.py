@@ -75,7 +75,8 @@ def test_host_tables_match_oracle(sh):
 @pytest.mark.parametrize("bad", [dict(nlon=7), dict(nlat=5), dict(nlon=0), dict(nlev=0),
                                  dict(nlev=129), dict(thickness=-1.0), dict(K=0.0),
                                  dict(omega=2.5), dict(nu_pre=0), dict(max_iters=500),
-                                 dict(semi_threshold=0.0)])
+                                 dict(semi_threshold=0.0), dict(staged_columns=-1),
+                                 dict(smooth_interval=(2.0, 1.0))])
 def test_host_argument_validation(bad):
     ensure_library()
     from paper_2307_04528_amd import mg_plan
