@@ -118,6 +118,13 @@ def main():
                     help="per-sweep damping factors from the Chebyshev nodes of [LO, HI] "
                          "(default 1/3,2, the library default); 'none': every sweep "
                          "uses omega 0.8")
+    ap.add_argument("--levels", type=int, default=0,
+                    help="hierarchy depth: 0 = automatic (default), n = at most n levels "
+                         "(the paper's shallow hierarchy is 4)")
+    ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
+                    help="the timed solve: FP32 V-cycle inside FP64 refinement (default), "
+                         "or everything in FP32 (its residual stalls near 1e-4 relative: "
+                         "use --tol above that)")
     args = ap.parse_args()
     smooth = None
     if args.smooth_interval != "none":
@@ -151,7 +158,8 @@ def main():
 
     t0 = time.perf_counter()
     S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
-                          precision="mixed", profile=True, smooth_interval=smooth)
+                          precision=args.precision, profile=True, smooth_interval=smooth,
+                          levels=args.levels)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup * 1e3:.1f} ms")
@@ -175,7 +183,7 @@ def main():
             f"iters {stats[-1].iters}, relres {stats[-1].relres:.2e}")
         return times, stats, total
 
-    times, stats, total = run(S, args.steps, args.warmup, "mixed")
+    times, stats, total = run(S, args.steps, args.warmup, args.precision)
     u_mixed = u.clone()
     mean_s = total / args.steps
     st = stats[-1]
@@ -184,11 +192,13 @@ def main():
         "metric": METRIC, "value": mean_s, "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mean_s * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "dtype": "f32+f64" if args.precision == "mixed" else "f32", "data": "synthetic",
         "config": {"workload": sh.name, "grid": [sh.nlon, sh.nlat, sh.nlev],
                    "unknowns": sh.n, "cycle": f"V({sh.nu_pre},{sh.nu_post})",
                    "tol": args.tol, "levels": st.levels, "iters": st.iters,
-                   "precision": "FP32 V-cycle inside FP64 refinement",
+                   "hierarchy": "automatic" if args.levels == 0 else f"at most {args.levels} levels",
+                   "precision": ("FP32 V-cycle inside FP64 refinement"
+                                 if args.precision == "mixed" else "FP32 throughout"),
                    "smoothing": (f"Chebyshev factors on [{smooth[0]:g}, {smooth[1]:g}]"
                                  if smooth else "omega 0.8 every sweep")},
         "median_s": statistics.median(times),
@@ -212,7 +222,8 @@ def main():
 
     if not args.no_fp64:
         S64 = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
-                                precision="fp64", profile=True, smooth_interval=smooth)
+                                precision="fp64", profile=True, smooth_interval=smooth,
+                                levels=args.levels)
         times64, stats64, total64 = run(S64, args.steps, args.warmup, "fp64")
         d = (u - u_mixed).norm() / u.norm()
         out["fp64_solve_s"] = total64 / args.steps

@@ -16,7 +16,7 @@
  * horizontal anisotropy of a row is small (conditional semi-coarsening);
  * run V-cycles with a few smoother sweeps on the coarsest level. The V-cycle
  * runs in FP32 inside an FP64 iterative-refinement loop (residual and update
- * in FP64), or entirely in FP64.
+ * in FP64), entirely in FP64, or entirely in FP32.
  *
  * Conventions for every entry point:
  *  - Field arguments are caller-owned DEVICE pointers holding N =
@@ -56,7 +56,16 @@ typedef enum {
 
 typedef enum {
     MG_PREC_MIXED = 0,        /* FP32 V-cycle inside FP64 refinement */
-    MG_PREC_FP64 = 1          /* everything in FP64 */
+    MG_PREC_FP64 = 1,         /* everything in FP64 */
+    MG_PREC_FP32 = 2          /* everything in FP32: b and u are cast to FP32
+                                 on entry (u back on exit), the residual is
+                                 FP32 (its norm summed in FP64). Contracts
+                                 like MG_PREC_MIXED until the residual meets
+                                 the floor set by rounding u to FP32,
+                                 ||H (u - fl32(u))|| / ||b|| (1e-4 to 4e-4
+                                 on the synthetic shells), then stays there;
+                                 tighter tolerances end in
+                                 MG_ERR_NOT_CONVERGED */
 } mg_precision;
 
 /* Grid of the shell.
@@ -137,7 +146,8 @@ enum {
 
 /* Statistics of one solve.
  * iters       : outer iterations performed.
- * relres      : final ||b - H u||_2 / ||b||_2 (FP64, unweighted 2-norm).
+ * relres      : final ||b - H u||_2 / ||b||_2 (unweighted 2-norm; the
+ *               residual in FP64, in FP32 for MG_PREC_FP32; sums in FP64).
  * res_hist    : ||r_m||_2 for m = 0..iters.
  * ms_total    : wall time of the solve on the host clock (ms).
  * levels_used : levels in the hierarchy.

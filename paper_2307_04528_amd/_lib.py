@@ -20,7 +20,7 @@ KERNEL_CLASSES = ["residual64", "smooth", "restrict", "prolong", "coarse", "adjo
 
 MG_OK, MG_ERR_NOT_CONVERGED = 0, 1
 MG_ERR_ARG, MG_ERR_HIP, MG_ERR_OOM, MG_ERR_BREAKDOWN = -1, -2, -3, -4
-MG_PREC_MIXED, MG_PREC_FP64 = 0, 1
+MG_PREC_MIXED, MG_PREC_FP64, MG_PREC_FP32 = 0, 1, 2
 
 
 class mg_grid(C.Structure):

@@ -8,6 +8,13 @@
 
 namespace mgk {
 
+#ifndef MG_RESIDUAL_BLOCK
+#define MG_RESIDUAL_BLOCK 256
+#endif
+// Threads of a k_residual_update block: one wavefront per row of the block's
+// tile, so the tile spans kResidualBlock / 64 consecutive rows.
+constexpr int kResidualBlock = MG_RESIDUAL_BLOCK;
+
 namespace {
 using namespace dev;
 
@@ -33,47 +40,49 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __res
     y[t] = HAS_F ? f[t] - h : h;
 }
 
-// FP64 refinement step on the finest level, one lane per column (row-tiled
-// segments, one wavefront per row of the block's tile):
+// Refinement step on the finest level, one lane per column (row-tiled
+// segments, one wavefront per row of the block's tile), in the precision TU
+// of the iterate (FP64; FP32 in the pure single-precision solve):
 //   unew = uin + e (HAS_E; written to uout), r = b - H unew (stored as TR),
 //   per-block partial sums of r^2 in FP64.
-template <typename TE, typename TR, int NZ, bool HAS_E>
-__global__ __launch_bounds__(kBlock) void k_residual_update(
-    LevelView<double> L, const double* __restrict__ bv, const double* __restrict__ uin,
-    const TE* __restrict__ e, double* __restrict__ uout, TR* __restrict__ r,
+template <typename TU, typename TE, typename TR, int NZ, bool HAS_E>
+__global__ __launch_bounds__(kResidualBlock) void k_residual_update(
+    LevelView<TU> L, const TU* __restrict__ bv, const TU* __restrict__ uin,
+    const TE* __restrict__ e, TU* __restrict__ uout, TR* __restrict__ r,
     double* __restrict__ partials, int wpr) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const Seg g = tiled_segment(int(logical_block()), wave, kBlock / 64, L.nI, L.nJ, wpr);
+    const Seg g = tiled_segment(int(logical_block()), wave, kResidualBlock / 64, L.nI, L.nJ, wpr);
     double acc = 0;
     {
         const Seg& nb = g;
-        const NbB<double> b8(nb);
+        const NbB<TU> bu(nb);
         const NbB<TE> be(nb);
         const NbB<TR> br(nb);
         const int nJ = L.nJ, nz = L.nz;
-        const uint64_t P8 = uint64_t(L.plane) * 8, PE = uint64_t(L.plane) * sizeof(TE),
+        const uint64_t PU = uint64_t(L.plane) * sizeof(TU),
+                       PE = uint64_t(L.plane) * sizeof(TE),
                        PR = uint64_t(L.plane) * sizeof(TR);
-        auto un = [&](int kk, uint32_t o8, uint32_t oe) -> double {
-            double v = ldb<double>(layer(uin, kk, P8), o8);
-            if constexpr (HAS_E) v += double(ldb<TE>(layer(e, kk, PE), oe));
+        auto un = [&](int kk, uint32_t ou, uint32_t oe) -> TU {
+            TU v = ldb<TU>(layer(uin, kk, PU), ou);
+            if constexpr (HAS_E) v += TU(ldb<TE>(layer(e, kk, PE), oe));
             return v;
         };
-        double um = 0, uc = un(0, b8.c, be.c);
+        TU um = 0, uc = un(0, bu.c, be.c);
 #pragma unroll
         for (int k = 0; k < NZ; ++k) {
             const int kk = clampk(k, nz), kp = clampk(k + 1, nz);
-            const double up = un(kp, b8.c, be.c);
-            const double h =
-                ldb<double>(layer(L.M, kk, P8), b8.c) * uc +
+            const TU up = un(kp, bu.c, be.c);
+            const TU h =
+                ldb<TU>(layer(L.M, kk, PU), bu.c) * uc +
                 hdiff(tab(L.Tlam, kk * nJ + nb.J), tab(L.Tth, kk * (nJ + 1) + nb.J),
-                      tab(L.Tth, kk * (nJ + 1) + nb.J + 1), uc, un(kk, b8.w, be.w),
-                      un(kk, b8.e, be.e), un(kk, b8.s, be.s), un(kk, b8.n, be.n)) +
+                      tab(L.Tth, kk * (nJ + 1) + nb.J + 1), uc, un(kk, bu.w, be.w),
+                      un(kk, bu.e, be.e), un(kk, bu.s, be.s), un(kk, bu.n, be.n)) +
                 tab(L.Tr, kk * nJ + nb.J) * (uc - um) + tab(L.Tr, (kk + 1) * nJ + nb.J) * (uc - up);
-            const double rv = ldb<double>(layer(bv, kk, P8), b8.c) - h;
+            const TU rv = ldb<TU>(layer(bv, kk, PU), bu.c) - h;
             if (k < nz && g.valid) {
-                if constexpr (HAS_E) stb<double>(layer_w(uout, kk, P8), b8.c, uc);
+                if constexpr (HAS_E) stb<TU>(layer_w(uout, kk, PU), bu.c, uc);
                 stb<TR>(layer_w(r, kk, PR), br.c, TR(rv));
-                acc += rv * rv;
+                acc += double(rv) * double(rv);
             }
             um = uc;
             uc = up;
@@ -220,25 +229,26 @@ void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
     else k_apply<T, false><<<blocks_for(n), kBlock, 0, s>>>(L, x, f, y, uint32_t(n));
 }
 
-template <typename TE, typename TR>
-int residual_update(const LevelView<double>& L, const double* b, const double* uin,
-                    const TE* e, double* uout, TR* r, double* partials, hipStream_t s) {
+template <typename TU, typename TE, typename TR>
+int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE* e, TU* uout,
+                    TR* r, double* partials, hipStream_t s) {
     const int wpr = segments_per_row(L.nI);
     const int nb = residual_update_blocks(L);
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         if (e)
-            k_residual_update<TE, TR, NZ, true><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r,
-                                                                     partials, wpr);
+            k_residual_update<TU, TE, TR, NZ, true>
+                <<<nb, kResidualBlock, 0, s>>>(L, b, uin, e, uout, r, partials, wpr);
         else
-            k_residual_update<TE, TR, NZ, false><<<nb, kBlock, 0, s>>>(L, b, uin, e, uout, r,
-                                                                      partials, wpr);
+            k_residual_update<TU, TE, TR, NZ, false>
+                <<<nb, kResidualBlock, 0, s>>>(L, b, uin, e, uout, r, partials, wpr);
     });
     return nb;
 }
 
-int residual_update_blocks(const LevelView<double>& L) {
-    return tiled_blocks(L.nJ, segments_per_row(L.nI), kBlock / 64);
+template <typename TU>
+int residual_update_blocks(const LevelView<TU>& L) {
+    return tiled_blocks(L.nJ, segments_per_row(L.nI), kResidualBlock / 64);
 }
 
 int norm2_partials(const double* x, long long n, double* partials, hipStream_t s) {
@@ -289,12 +299,18 @@ template void apply<float>(const LevelView<float>&, const float*, const float*, 
                            hipStream_t);
 template void apply<double>(const LevelView<double>&, const double*, const double*, double*,
                             hipStream_t);
-template int residual_update<float, float>(const LevelView<double>&, const double*,
-                                           const double*, const float*, double*, float*,
-                                           double*, hipStream_t);
-template int residual_update<double, double>(const LevelView<double>&, const double*,
-                                             const double*, const double*, double*,
-                                             double*, double*, hipStream_t);
+template int residual_update<double, float, float>(const LevelView<double>&, const double*,
+                                                  const double*, const float*, double*,
+                                                  float*, double*, hipStream_t);
+template int residual_update<double, double, double>(const LevelView<double>&,
+                                                     const double*, const double*,
+                                                     const double*, double*, double*,
+                                                     double*, hipStream_t);
+template int residual_update<float, float, float>(const LevelView<float>&, const float*,
+                                                 const float*, const float*, float*, float*,
+                                                 double*, hipStream_t);
+template int residual_update_blocks<double>(const LevelView<double>&);
+template int residual_update_blocks<float>(const LevelView<float>&);
 template void cast<double, float>(const double*, float*, long long, hipStream_t);
 template void cast<float, double>(const float*, double*, long long, hipStream_t);
 template void cast<double, double>(const double*, double*, long long, hipStream_t);

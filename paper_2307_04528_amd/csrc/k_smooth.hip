@@ -48,6 +48,9 @@ namespace mgk {
 #ifndef MG_RAW32
 #define MG_RAW32 0
 #endif
+#ifndef MG_XLDS32
+#define MG_XLDS32 0
+#endif
 #ifndef MG_RAW64
 #define MG_RAW64 1
 #endif
@@ -237,19 +240,28 @@ template <typename T>
 struct KeepX {
     static constexpr bool value = std::is_same<T, float>::value ? true : (MG_KEEPX64 != 0);
 };
+// Where a kept old iterate lives: in LDS (one 64-lane row per step of the
+// wavefront) instead of registers, which frees the registers for a fourth
+// wavefront per SIMD (FP32, up to 72 layers: 16 wavefronts need 144 KiB).
+template <typename T, int NZ>
+struct KeepXInLds {
+    static constexpr bool value = std::is_same<T, float>::value && NZ <= 72 && MG_XLDS32 != 0;
+};
 
 // One sweep of the segment's columns (see the file comment); HAS_X false:
 // the sweep from zero, omega H_z^{-1} f.
 template <typename T, int NZ, int D, bool HAS_X>
 __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f, const T* xin,
                                               T* xout, T omega, const Seg& g, bool top,
-                                              T* xch) {
+                                              T* xch, T* xlds) {
     const NbB<T> b(g);
     const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
     constexpr bool KX = HAS_X && KeepX<T>::value;
-    T xk[KX ? padded_steps<NZ, D>() : 1];
+    constexpr bool XL = KX && KeepXInLds<T, NZ>::value;
+    const int lane = int(threadIdx.x & 63u);
+    T xk[KX && !XL ? padded_steps<NZ, D>() : 1];
     auto fetch = [&](int, int kk) {
         StencilRaw<T> r{};
         r.f = ldb<T>(layer(f, kk, Pb), b.c);
@@ -280,7 +292,8 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
                 s += tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
                      tab(L.Tth, kk * (nJ + 1) + J) * r.s +
                      tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
-            if constexpr (KX) xk[t] = r.c;
+            if constexpr (XL) xlds[t * 64 + lane] = r.c;
+            else if constexpr (KX) xk[t] = r.c;
         }
         return s;
     };
@@ -293,7 +306,8 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
     auto bload = [&](int kk) -> T { return ldb<T>(layer(xin, kk, Pb), b.c); };
     auto sink = [&](int t, int kk, T z, T e) {
         T out = omega * z;
-        if constexpr (KX) out += keep * xk[t];
+        if constexpr (XL) out += keep * xlds[t * 64 + lane];
+        else if constexpr (KX) out += keep * xk[t];
         else if constexpr (HAS_X) out += keep * e;
         if (g.valid) stb<T>(layer_w(xout, kk, Pb), b.c, out);
     };
@@ -321,9 +335,12 @@ void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin
               T* __restrict__ xout, T omega, int wpr) {
     constexpr int PB = PairsPerBlock<T>::value;
     __shared__ T xch[PB][256];
+    constexpr bool XL = HAS_X && KeepX<T>::value && KeepXInLds<T, NZ>::value;
+    __shared__ T xlds[XL ? 2 * PB : 1][XL ? padded_steps<NZ, D>() * 64 : 1];
     const PairOf p = pair_of_wave();
     const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
-    sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
+    sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair],
+                                   xlds[XL ? 2 * p.pair + int(p.top) : 0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,7 +500,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
                                                        T* xa, T* xb, T omega, int sweeps,
                                                        int wpr) {
     __shared__ T xch[kBlock / 128][256];
+    constexpr bool XL = KeepX<T>::value && KeepXInLds<T, NZ>::value;
+    __shared__ T xlds[XL ? kBlock / 64 : 1][XL ? padded_steps<NZ, D>() * 64 : 1];
     const PairOf p = pair_of_wave();
+    T* xl = xlds[XL ? 2 * p.pair + int(p.top) : 0];
     const int nseg = L.nJ * wpr;
     for (int s = 0; s < sweeps; ++s) {
         T* xout = (s & 1) ? xb : xa;
@@ -491,9 +511,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
         for (int s0 = 0; s0 < nseg; s0 += kBlock / 128) {
             const Seg g = segment(s0 + p.pair, L.nI, L.nJ, wpr);
             if (s == 0)
-                sweep_segment<T, NZ, D, false>(L, f, nullptr, xout, omega, g, p.top, xch[p.pair]);
+                sweep_segment<T, NZ, D, false>(L, f, nullptr, xout, omega, g, p.top, xch[p.pair],
+                                               xl);
             else
-                sweep_segment<T, NZ, D, true>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
+                sweep_segment<T, NZ, D, true>(L, f, xin, xout, omega, g, p.top, xch[p.pair], xl);
             __syncthreads();
         }
     }

@@ -123,15 +123,17 @@ void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout
 template <typename T>
 void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s);
 
-// FP64 refinement step on the finest level:
+// Refinement step on the finest level, in the iterate's precision TU (FP64;
+// FP32 in the pure single-precision solve):
 //   unew = uin + e (or uin when e == nullptr), written to uout if set;
 //   r = b - H unew, stored as TR; per-block partial sums of r^2 in FP64.
 // Returns the number of blocks (partials written).
-template <typename TE, typename TR>
-int residual_update(const LevelView<double>& L, const double* b, const double* uin,
-                    const TE* e, double* uout, TR* r, double* partials, hipStream_t s);
+template <typename TU, typename TE, typename TR>
+int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE* e, TU* uout,
+                    TR* r, double* partials, hipStream_t s);
 // Blocks (hence partial sums) residual_update launches for level L.
-int residual_update_blocks(const LevelView<double>& L);
+template <typename TU>
+int residual_update_blocks(const LevelView<TU>& L);
 
 // Per-block partial sums of x^2.
 int norm2_partials(const double* x, long long n, double* partials, hipStream_t s);

@@ -194,8 +194,9 @@ std::string validate(const mg_grid& g, const mg_options& o) {
     if (!(o.omega > 0 && o.omega < 2)) return "omega must be in (0, 2)";
     if (!(o.semi_threshold > 0) || !std::isfinite(o.semi_threshold))
         return "semi_threshold must be finite and > 0";
-    if (o.precision != MG_PREC_MIXED && o.precision != MG_PREC_FP64)
-        return "precision must be MG_PREC_MIXED or MG_PREC_FP64";
+    if (o.precision != MG_PREC_MIXED && o.precision != MG_PREC_FP64 &&
+        o.precision != MG_PREC_FP32)
+        return "precision must be MG_PREC_MIXED, MG_PREC_FP64 or MG_PREC_FP32";
     if (o.smooth_lo != 0.0 &&
         !(o.smooth_lo > 0 && o.smooth_hi > o.smooth_lo && std::isfinite(o.smooth_hi)))
         return "smoothing interval must be 0 or 0 < smooth_lo < smooth_hi";

@@ -88,6 +88,7 @@ struct mg_handle {
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
     double* u_alt = nullptr;       // FP64 ping-pong partner of the caller's u
+    float *u32a = nullptr, *u32b = nullptr, *b32 = nullptr;   // MG_PREC_FP32 solve
     double* partials = nullptr;
     double* scalar = nullptr;      // device: reduced value
     double* host_scalar = nullptr; // pinned host copy
@@ -483,16 +484,20 @@ mg_status norm2(mg_handle* h, const double* x, long long n, double* out) {
 }
 
 // FP64 update + residual step; returns ||r||.
-template <typename T>
-mg_status refine_step(mg_handle* h, const double* b, const double* uin, const T* e,
-                      double* uout, T* r, double* rnorm) {
+// One refinement step with the iterate, b and H in precision U (FP64, or
+// FP32 in the pure single-precision solve) and the correction e and
+// residual r in the V-cycle's precision T.
+template <typename T, typename U>
+mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r,
+                      double* rnorm) {
     DevLevel& d = h->lv[0];
-    const double bytes = double(d.n) * (8 + 8 + 8 + sizeof(T) + (e ? sizeof(T) + 8 : 0));
+    const double bytes =
+        double(d.n) * (3 * sizeof(U) + sizeof(T) + (e ? sizeof(T) + sizeof(U) : 0));
     int nb = 0;
     {
         Launch g(h, MG_K_RESIDUAL64, 0, bytes);
-        nb = mgk::residual_update<T, T>(view<double>(d), b, uin, e, uout, r, h->partials,
-                                        h->stream);
+        nb = mgk::residual_update<U, T, T>(view<U>(d), b, uin, e, uout, r, h->partials,
+                                           h->stream);
     }
     MG_TRY(check_launch(h, "residual_update"));
     {
@@ -505,9 +510,11 @@ mg_status refine_step(mg_handle* h, const double* b, const double* uin, const T*
     return MG_OK;
 }
 
-// The outer refinement loop in precision T, with the forward (transposed =
-// false) or transposed V-cycle.
-template <typename T>
+// The outer refinement loop: V-cycles in precision T, the iterate and its
+// residual in precision U (FP64; FP32 for MG_PREC_FP32, where b and u are
+// cast on entry and u back on exit), with the forward (transposed = false)
+// or transposed V-cycle.
+template <typename T, typename U>
 mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* st,
                 bool transposed) {
     MG_TRY(ensure_work<T>(h));
@@ -517,13 +524,33 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     prof_reset(h);
     double bnorm = 0;
     MG_TRY(norm2(h, b, d.n, &bnorm));
+    const U* bU = nullptr;
+    U *ucur = nullptr, *unext = nullptr;
+    if constexpr (std::is_same<U, double>::value) {
+        bU = b;
+        ucur = u;
+        unext = h->u_alt;
+    } else {
+        if (!h->b32) {
+            MG_TRY(dalloc(h, &h->b32, d.n));
+            MG_TRY(dalloc(h, &h->u32a, d.n));
+            MG_TRY(dalloc(h, &h->u32b, d.n));
+        }
+        {
+            Launch g(h, MG_K_OTHER, 0, double(d.n) * 24);
+            mgk::cast<double, float>(b, h->b32, d.n, h->stream);
+            mgk::cast<double, float>(u, h->u32a, d.n, h->stream);
+        }
+        MG_TRY(check_launch(h, "cast"));
+        bU = h->b32;
+        ucur = h->u32a;
+        unext = h->u32b;
+    }
     // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
     T* r = transposed ? w.xbar : w.f;
     double rn = 0;
-    MG_TRY(refine_step<T>(h, b, u, nullptr, nullptr, r, &rn));
+    MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r, &rn)));
     std::vector<double> hist{rn};
-    double* ucur = u;
-    double* unext = h->u_alt;
     int it = 0;
     mg_status status = MG_OK;
     if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
@@ -542,16 +569,24 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
             MG_TRY(vcycle_T<T>(h, 0));
             e = w.fbar;
         }
-        MG_TRY(refine_step<T>(h, b, ucur, e, unext, r, &rn));
+        MG_TRY((refine_step<T, U>(h, bU, ucur, e, unext, r, &rn)));
         std::swap(ucur, unext);
         ++it;
         hist.push_back(rn);
         if (!std::isfinite(rn)) status = MG_ERR_BREAKDOWN;
     }
-    if (ucur != u) {
-        Launch g(h, MG_K_OTHER, 0, double(d.n) * 16);
-        HIP_TRY(h, hipMemcpyAsync(u, ucur, d.n * sizeof(double), hipMemcpyDeviceToDevice,
-                                  h->stream));
+    if constexpr (std::is_same<U, double>::value) {
+        if (ucur != u) {
+            Launch g(h, MG_K_OTHER, 0, double(d.n) * 16);
+            HIP_TRY(h, hipMemcpyAsync(u, ucur, d.n * sizeof(double), hipMemcpyDeviceToDevice,
+                                      h->stream));
+        }
+    } else {
+        {
+            Launch g(h, MG_K_OTHER, 0, double(d.n) * 12);
+            mgk::cast<float, double>(ucur, u, d.n, h->stream);
+        }
+        MG_TRY(check_launch(h, "cast"));
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     auto t1 = std::chrono::steady_clock::now();
@@ -851,8 +886,10 @@ static mg_status solve_common(mg_handle* h, const double* rhs, double* u, double
     if (!(tol > 0) || !std::isfinite(tol)) return fail(h, MG_ERR_ARG, "tol must be > 0");
     if (rhs == u) return fail(h, MG_ERR_ARG, "rhs and solution must not alias");
     if (h->opt.precision == MG_PREC_FP64)
-        return outer<double>(h, rhs, u, tol, st, transposed);
-    return outer<float>(h, rhs, u, tol, st, transposed);
+        return outer<double, double>(h, rhs, u, tol, st, transposed);
+    if (h->opt.precision == MG_PREC_FP32)
+        return outer<float, float>(h, rhs, u, tol, st, transposed);
+    return outer<float, double>(h, rhs, u, tol, st, transposed);
 }
 
 mg_status mg_solve(mg_handle* h, const double* rhs, double* u, double tol, mg_stats* st) {

@@ -56,7 +56,8 @@ def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, ome
     o.nu_pre, o.nu_post = int(nu_pre), int(nu_post)
     o.coarse_sweeps, o.max_iters = int(coarse_sweeps), int(max_iters)
     o.omega, o.semi_threshold = float(omega), float(semi_threshold)
-    o.precision = {"mixed": L.MG_PREC_MIXED, "fp64": L.MG_PREC_FP64}[precision]
+    o.precision = {"mixed": L.MG_PREC_MIXED, "fp64": L.MG_PREC_FP64,
+                   "fp32": L.MG_PREC_FP32}[precision]
     o.stream = stream
     o.profile = int(profile)
     if smooth_interval is None:
