@@ -103,6 +103,43 @@ def cpu_baseline(shell, iters_gpu, smooth):
             "per_iteration_s": t_iter}
 
 
+def timestep_run(S, sh, alpha0, b0, steps, tol):
+    """Steps 1..steps of shellgen.timestep: per step, the coefficient update
+    (masses, pivots, coarsest matrix) and the solve warm-started from the
+    previous step's solution, each timed with a device synchronisation. The
+    inputs are resident in HBM before the first step."""
+    import torch
+    import shellgen
+    seq = [tuple(torch.from_numpy(x).to(b0.device) for x in shellgen.timestep(sh, t))
+           for t in range(1, steps + 1)]
+    S.update_alpha(alpha0)
+    u = torch.zeros_like(b0)
+    _, st0 = S.solve(b0, tol=tol, out=u)
+    torch.cuda.synchronize()
+    upd, sol, iters = [], [], []
+    for a_t, b_t in seq:
+        t0 = time.perf_counter()
+        S.update_alpha(a_t)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = S.solve(b_t, tol=tol, u0=u, out=u)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        upd.append(t1 - t0)
+        sol.append(t2 - t1)
+        iters.append(st.iters)
+    ucold = torch.zeros_like(b0)
+    _, stc = S.solve(seq[-1][1], tol=tol, out=ucold)
+    S.update_alpha(alpha0)
+    log(f"timesteps: {steps} steps, update {statistics.mean(upd)*1e3:.2f} ms, warm solve "
+        f"{statistics.mean(sol)*1e3:.2f} ms, iters {iters} (cold {stc.iters})")
+    return {"steps": steps, "drift": 0.02, "tol": tol,
+            "ms_per_step": (sum(upd) + sum(sol)) / steps * 1e3,
+            "update_ms": statistics.mean(upd) * 1e3, "solve_ms": statistics.mean(sol) * 1e3,
+            "iters": iters, "first_step_cold_iters": st0.iters,
+            "last_step_cold_iters": stc.iters}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +162,10 @@ def main():
                     help="the timed solve: FP32 V-cycle inside FP64 refinement (default), "
                          "or everything in FP32 (its residual stalls near 1e-4 relative: "
                          "use --tol above that)")
+    ap.add_argument("--timesteps", type=int, default=0, metavar="K",
+                    help="also time K steps of a slowly varying sequence (alpha and b drift "
+                         "by 2 %% per step): coefficient update plus a solve warm-started "
+                         "from the previous step's solution")
     args = ap.parse_args()
     smooth = None
     if args.smooth_interval != "none":
@@ -231,6 +272,9 @@ def main():
         out["speedup_vs_fp64"] = (total64 / args.steps) / mean_s
         out["mixed_vs_fp64_rel_diff"] = float(d)
         S64.close()
+
+    if args.timesteps > 0:
+        out["timestep"] = timestep_run(S, sh, alpha, b, args.timesteps, args.tol)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sh, st.iters, smooth)

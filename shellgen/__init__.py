@@ -21,13 +21,15 @@ import numpy as np
 
 __all__ = [
     "Shell", "WORKLOADS", "workload", "rhs", "alpha", "weights",
-    "fd_direction", "SEED_RHS", "SEED_ALPHA", "SEED_W", "SEED_FD0",
+    "fd_direction", "timestep", "SEED_RHS", "SEED_ALPHA", "SEED_W", "SEED_FD0",
+    "SEED_STEP0",
 ]
 
 SEED_RHS = 1
 SEED_ALPHA = 2
 SEED_W = 3
 SEED_FD0 = 100
+SEED_STEP0 = 1000
 
 
 @dataclass(frozen=True)
@@ -111,3 +113,15 @@ def weights(shell: Shell, seed: int = SEED_W) -> np.ndarray:
 def fd_direction(shell: Shell, m: int) -> np.ndarray:
     """Finite-difference direction number m ~ N(0,1), seed 100+m."""
     return np.random.default_rng(SEED_FD0 + m).standard_normal(size=shell.shape)
+
+
+def timestep(shell: Shell, t: int, drift: float = 0.02) -> tuple[np.ndarray, np.ndarray]:
+    """Inputs of step t >= 1 of a sequence of solves whose coefficients and
+    right-hand side vary slowly, as in the solves of consecutive semi-implicit
+    time steps (Section 1):
+        alpha_t = alpha * (1 + drift * p_t),  p_t ~ U[-1,1], seed SEED_STEP0 + 2t
+        b_t     = b + drift * q_t,            q_t ~ U[-1,1], seed SEED_STEP0 + 2t + 1
+    with alpha = alpha(shell) and b = rhs(shell). Every alpha_t stays > 0."""
+    p = np.random.default_rng(SEED_STEP0 + 2 * t).uniform(-1.0, 1.0, size=shell.shape)
+    q = np.random.default_rng(SEED_STEP0 + 2 * t + 1).uniform(-1.0, 1.0, size=shell.shape)
+    return alpha(shell) * (1.0 + drift * p), rhs(shell) + drift * q

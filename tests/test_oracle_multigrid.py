@@ -219,3 +219,25 @@ def test_chebyshev_vcycle_transpose_and_convergence(nu):
         rho_c = convergence_factors(st_c["res_hist"])[-3:]
         rho_t = convergence_factors(st_t["res_hist"])[-3:]
         assert rho_t.max() < 0.12 and rho_t.max() < 0.8 * rho_c.min(), (rho_c, rho_t)
+
+
+def test_timestep_inputs_and_warm_start():
+    """The time-step sequence (shellgen.timestep): seeded, alpha_t > 0 within
+    2 % of alpha, b_t within 0.02 of b; the oracle's solve of step t started
+    from the solution of step t-1 needs fewer iterations than from zero."""
+    sh = shellgen.workload("shell64x32x16")
+    a0, b0 = shellgen.alpha(sh), shellgen.rhs(sh)
+    opt = Options(nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    u, _ = solve(build_hierarchy(sh, a0), b0, opt, tol=1e-8)
+    for step in (1, 2):
+        a, b = shellgen.timestep(sh, step)
+        a2, b2 = shellgen.timestep(sh, step)
+        assert np.array_equal(a, a2) and np.array_equal(b, b2)
+        assert (a > 0).all() and np.abs(a / a0 - 1).max() <= 0.02
+        assert np.abs(b - b0).max() <= 0.02
+        Lt = build_hierarchy(sh, a)
+        uw, sw = solve(Lt, b, opt, tol=1e-8, u0=u)
+        _, sc = solve(Lt, b, opt, tol=1e-8)
+        assert sw["relres"] <= 1e-8
+        assert sw["iters"] < sc["iters"]
+        u = uw
