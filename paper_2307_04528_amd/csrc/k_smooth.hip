@@ -528,7 +528,9 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
 // iterate; a sweep then costs a few microseconds.
 // UNIT: block b solves for the b-th unit vector instead of f and writes its
 // result to row b of xout (rows of n values): the grid then computes the
-// solve's explicit matrix, transposed, one row per block.
+// solve's explicit matrix, transposed, one row per block. The unit
+// right-hand side is formed on the fly, not stored: the smaller LDS
+// footprint lets two blocks share a CU on more levels.
 template <typename T, int NZ, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* __restrict__ f,
                                                        T* __restrict__ xout, T omega,
@@ -537,16 +539,15 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     const int plane = int(L.plane), nz = L.nz, nJ = L.nJ, n = plane * nz;
     if constexpr (UNIT) xout += size_t(blockIdx.x) * size_t(n);
     T* sx = reinterpret_cast<T*>(smem_raw);
-    T* sf = sx + n;
-    T* sp = sf + n;
+    T* sf = sx + n;                  // right-hand side (not UNIT)
+    T* sp = sf + (UNIT ? 0 : n);
     T* stl = sp + n;                 // [nz][nJ]
     T* sth = stl + nz * nJ;          // [nz][nJ+1]
     T* str = sth + nz * (nJ + 1);    // [nz+1][nJ]
     T* xch = str + (nz + 1) * nJ;    // 256 per pair
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         sx[t] = T(0);   // the first sweep starts from zero: same code as the rest
-        if constexpr (UNIT) sf[t] = (t == int(blockIdx.x)) ? T(1) : T(0);
-        else sf[t] = f[t];
+        if constexpr (!UNIT) sf[t] = f[t];
         sp[t] = L.invp[t];
     }
     for (int t = threadIdx.x; t < nz * nJ; t += blockDim.x) stl[t] = L.Tlam[t];
@@ -575,7 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
         auto fetch = [&](int, int kk) {
             const T* xl = sx + kk * pl;
             StencilRaw<T> r;
-            r.f = sf[kk * pl + b.c];
+            if constexpr (UNIT) r.f = (kk * pl + int(b.c) == int(blockIdx.x)) ? T(1) : T(0);
+            else r.f = sf[kk * pl + b.c];
             r.c = xl[b.c];
             r.w = xl[b.w];
             r.e = xl[b.e];
@@ -758,7 +760,7 @@ void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
 template <typename T, bool UNIT>
 bool launch_coarse_lds(const LevelView<T>& L, const T* f, T* x, T omega, int sweeps,
                        size_t max_lds, int blocks, hipStream_t s) {
-    const size_t lds = coarse_lds_bytes<T>(L.plane, L.nJ, L.nz);
+    const size_t lds = coarse_lds_bytes<T>(L.plane, L.nJ, L.nz, UNIT);
     if (L.plane > kCoarseLdsColumns || lds > max_lds) return false;
     const int threads = int((L.plane + 63) / 64) * 128;
     bool launched = false;

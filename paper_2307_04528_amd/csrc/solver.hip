@@ -715,7 +715,7 @@ mg_status build(mg_handle* h, const double* alpha) {
         DenseCoarse& D = h->dense;
         D.n = c.n;
         D.enabled = c.n <= mgk::kDenseCoarseMax && c.plane <= mgk::kCoarseLdsColumns &&
-                    mgk::coarse_lds_bytes<double>(c.plane, c.nJ, c.nz) <= h->max_lds;
+                    mgk::coarse_lds_bytes<double>(c.plane, c.nJ, c.nz, true) <= h->max_lds;
         if (D.enabled) {
             const size_t nn = size_t(c.n) * size_t(c.n);
             MG_TRY(dalloc(h, &D.C64, nn));
