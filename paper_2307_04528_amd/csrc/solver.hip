@@ -92,6 +92,7 @@ struct mg_handle {
     double* partials = nullptr;
     double* scalar = nullptr;      // device: reduced value
     double* host_scalar = nullptr; // pinned host copy
+    hipEvent_t scalar_ready = nullptr;   // recorded after the copy to host_scalar
     int max_partials = 0;
     size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
     bool have32 = false, have64 = false;
@@ -461,12 +462,25 @@ mg_status vcycle_T(mg_handle* h, int l) {
     return chain_T<T>(h, l, oms, false, &z);
 }
 
-mg_status sync_scalar(mg_handle* h, double* out) {
+// Copy the reduced scalar to the host (asynchronously; the copy's completion
+// is the event scalar_ready), and wait for it. Waiting on the event, not the
+// stream, lets work enqueued after the copy keep the GPU busy meanwhile.
+mg_status post_scalar(mg_handle* h) {
     HIP_TRY(h, hipMemcpyAsync(h->host_scalar, h->scalar, sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipEventRecord(h->scalar_ready, h->stream));
+    return MG_OK;
+}
+
+mg_status wait_scalar(mg_handle* h, double* out) {
+    HIP_TRY(h, hipEventSynchronize(h->scalar_ready));
     *out = *h->host_scalar;
     return MG_OK;
+}
+
+mg_status sync_scalar(mg_handle* h, double* out) {
+    MG_TRY(post_scalar(h));
+    return wait_scalar(h, out);
 }
 
 mg_status norm2(mg_handle* h, const double* x, long long n, double* out) {
@@ -487,9 +501,10 @@ mg_status norm2(mg_handle* h, const double* x, long long n, double* out) {
 // One refinement step with the iterate, b and H in precision U (FP64, or
 // FP32 in the pure single-precision solve) and the correction e and
 // residual r in the V-cycle's precision T.
+// Enqueues the step; its ||r||^2 reaches the host with post_scalar, read by
+// finish_step.
 template <typename T, typename U>
-mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r,
-                      double* rnorm) {
+mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r) {
     DevLevel& d = h->lv[0];
     const double bytes =
         double(d.n) * (3 * sizeof(U) + sizeof(T) + (e ? sizeof(T) + sizeof(U) : 0));
@@ -504,8 +519,12 @@ mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uou
         Launch g(h, MG_K_OTHER, 0, double(nb) * 8);
         mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
     }
+    return post_scalar(h);
+}
+
+mg_status finish_step(mg_handle* h, double* rnorm) {
     double s2 = 0;
-    MG_TRY(sync_scalar(h, &s2));
+    MG_TRY(wait_scalar(h, &s2));
     *rnorm = std::sqrt(s2);
     return MG_OK;
 }
@@ -549,27 +568,45 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
     T* r = transposed ? w.xbar : w.f;
     double rn = 0;
-    MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r, &rn)));
+    MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r)));
+    MG_TRY(finish_step(h, &rn));
     std::vector<double> hist{rn};
     int it = 0;
     mg_status status = MG_OK;
     if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
+    // enqueue one V-cycle on r; its correction e is what the next step adds
+    auto cycle = [&](const T** e) -> mg_status {
+        if (!transposed) {
+            T* x = nullptr;
+            MG_TRY(vcycle<T>(h, 0, w.f, &x));
+            *e = x;
+        } else {
+            MG_TRY(vcycle_T<T>(h, 0));
+            *e = w.fbar;
+        }
+        return MG_OK;
+    };
+    const T* e_ahead = nullptr;   // a V-cycle already enqueued on the current r
     while (status == MG_OK) {
         if (rn <= tol * bnorm) break;
         if (it >= h->opt.max_iters) {
             status = MG_ERR_NOT_CONVERGED;
             break;
         }
-        const T* e = nullptr;
-        if (!transposed) {
-            T* x = nullptr;
-            MG_TRY(vcycle<T>(h, 0, w.f, &x));
-            e = x;
-        } else {
-            MG_TRY(vcycle_T<T>(h, 0));
-            e = w.fbar;
-        }
-        MG_TRY((refine_step<T, U>(h, bU, ucur, e, unext, r, &rn)));
+        const T* e = e_ahead;
+        if (!e) MG_TRY(cycle(&e));
+        e_ahead = nullptr;
+        MG_TRY((refine_step<T, U>(h, bU, ucur, e, unext, r)));
+        // While the new norm travels to the host, keep the GPU busy with the
+        // next V-cycle when the residual is predicted to stay well above the
+        // tolerance (the last contraction factor carried forward). The
+        // update itself waits for the norm, so a cycle enqueued in vain
+        // costs time only, never the result.
+        const double rho = hist.size() >= 2 ? hist.back() / hist[hist.size() - 2] : 1.0;
+        if (it + 1 < h->opt.max_iters && std::isfinite(rho) &&
+            rn * std::min(rho, 1.0) > 3.0 * tol * bnorm)
+            MG_TRY(cycle(&e_ahead));
+        MG_TRY(finish_step(h, &rn));
         std::swap(ucur, unext);
         ++it;
         hist.push_back(rn);
@@ -702,6 +739,7 @@ mg_status build(mg_handle* h, const double* alpha) {
     MG_TRY(dalloc(h, &h->scalar, 1));
     MG_TRY(dalloc(h, &h->u_alt, f.n));
     HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, sizeof(double), hipHostMallocDefault));
+    HIP_TRY(h, hipEventCreateWithFlags(&h->scalar_ready, hipEventDisableTiming));
     {
         int dev = 0, lds = 0;
         HIP_TRY(h, hipGetDevice(&dev));
@@ -733,6 +771,8 @@ void release(mg_handle* h) {
     h->allocs.clear();
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
     h->host_scalar = nullptr;
+    if (h->scalar_ready) (void)hipEventDestroy(h->scalar_ready);
+    h->scalar_ready = nullptr;
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
 }
