@@ -1,7 +1,7 @@
 """Benchmark: time-to-solution of the shell multigrid solve on one MI355X.
 
 One step = one whole solve of H u = b from u = 0 to relative residual 1e-8
-(FP32 V(2,2) cycles inside the FP64 refinement loop) on the 1024x768x70 shell
+(FP32 V(2,3) cycles inside the FP64 refinement loop) on the 1024x768x70 shell
 (55M unknowns), with b and alpha already resident in HBM. The plain FP64
 multigrid solve of the same system is timed beside it, and every kernel
 launch of the timed region is bracketed by HIP events on the solver's stream

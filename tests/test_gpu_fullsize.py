@@ -35,13 +35,14 @@ def bench_levels():
 
 @functools.lru_cache(maxsize=1)
 def bench_vcycle_ref():
-    log("[oracle] one V(2,2) cycle on shell1024x768x70")
+    log(f"[oracle] one V({BENCH.nu_pre},{BENCH.nu_post}) cycle on shell1024x768x70")
     return oracle.vcycle(bench_levels(), shellgen.rhs(BENCH), opts_of(BENCH))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_bench_vcycle_full_field(prec):
-    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec)
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec, nu_pre=BENCH.nu_pre,
+                   nu_post=BENCH.nu_post)
     got = n(S.vcycle(t(shellgen.rhs(BENCH))))
     ref = bench_vcycle_ref()
     err = rel_inf(got, ref) if prec == "fp64" else rel2(got, ref)
@@ -101,7 +102,7 @@ def test_bench_coarser_level_sweeps(prec, staged):
 def test_mixed_solve_residual_checked_on_host(sh):
     log(f"[gpu] mixed solve of {sh.name} ({sh.n} cells)")
     a, b = shellgen.alpha(sh), shellgen.rhs(sh)
-    S = solver_for(sh, a, precision="mixed")
+    S = solver_for(sh, a, precision="mixed", nu_pre=sh.nu_pre, nu_post=sh.nu_post)
     u, st = S.solve(t(b), tol=1e-8)
     u = n(u)
     S.close()
