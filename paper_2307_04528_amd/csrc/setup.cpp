@@ -201,6 +201,7 @@ std::string validate(const mg_grid& g, const mg_options& o) {
         !(o.smooth_lo > 0 && o.smooth_hi > o.smooth_lo && std::isfinite(o.smooth_hi)))
         return "smoothing interval must be 0 or 0 < smooth_lo < smooth_hi";
     if (o.staged_columns < 0) return "staged_columns must be >= 0";
+    if (o.profile < 0 || o.profile > 3) return "profile must be 0, 1, 2 or 3";
     return "";
 }
 

@@ -232,7 +232,9 @@ struct Launch {
         h->alg_bytes += bytes;
         // profile 1: finest level only (no events around the short coarse
         // launches); 2: every launch
+        // 3: only the finest level's sweeps from an iterate
         if (!h->opt.profile || (h->opt.profile == 1 && level != 0)) return;
+        if (h->opt.profile == 3 && (level != 0 || cls != MG_K_SMOOTH)) return;
         rec.cls = cls;
         rec.level = level;
         rec.bytes = bytes;

@@ -76,6 +76,7 @@ def test_host_tables_match_oracle(sh):
                                  dict(nlev=129), dict(thickness=-1.0), dict(K=0.0),
                                  dict(omega=2.5), dict(nu_pre=0), dict(max_iters=500),
                                  dict(semi_threshold=0.0), dict(staged_columns=-1),
+                                 dict(profile=4),
                                  dict(smooth_interval=(2.0, 1.0))])
 def test_host_argument_validation(bad):
     ensure_library()
