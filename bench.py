@@ -103,6 +103,37 @@ def cpu_baseline(shell, iters_gpu, smooth):
             "per_iteration_s": t_iter}
 
 
+def oracle_solve(shell, tol, smooth, u_gpu):
+    """Small workloads (up to a million cells): the oracle's whole solve on
+    the host, beside the GPU's. Reports its iterations, contraction factors,
+    relative residual and time, the time of a sparse direct solve (scipy
+    splu of the assembled operator), and the GPU solution's relative
+    difference from the oracle's."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    import shellgen
+    import oracle
+    a, b = shellgen.alpha(shell), shellgen.rhs(shell)
+    L = oracle.build_hierarchy(shell, a)
+    opt = oracle.Options(nu_pre=shell.nu_pre, nu_post=shell.nu_post)
+    opt.smooth_lo, opt.smooth_hi = smooth if smooth else (0.0, 0.0)
+    t0 = time.perf_counter()
+    u, st = oracle.solve(L, b, opt, tol=tol)
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lu = spla.splu(oracle.assemble(L[0]).tocsc())
+    ud = lu.solve(b.ravel())
+    t_splu = time.perf_counter() - t0
+    rho = oracle.convergence_factors(st["res_hist"])
+    diff = float(np.linalg.norm(u_gpu - u) / np.linalg.norm(u))
+    log(f"oracle solve: {st['iters']} iterations, relres {st['relres']:.2e}, {t_solve:.2f}s; "
+        f"splu {t_splu:.2f}s; GPU vs oracle {diff:.2e}")
+    return {"iters": st["iters"], "relres": st["relres"], "seconds": t_solve, "cores": 1,
+            "factors": [float(x) for x in rho], "splu_seconds": t_splu,
+            "splu_vs_oracle": float(np.linalg.norm(ud - u.ravel()) / np.linalg.norm(ud)),
+            "gpu_vs_oracle": diff}
+
+
 def timestep_run(S, sh, alpha0, b0, steps, tol):
     """Steps 1..steps of shellgen.timestep: per step, the coefficient update
     (masses, pivots, coarsest matrix) and the solve warm-started from the
@@ -158,7 +189,7 @@ def main():
     ap.add_argument("--levels", type=int, default=0,
                     help="hierarchy depth: 0 = automatic (default), n = at most n levels "
                          "(the paper's shallow hierarchy is 4)")
-    ap.add_argument("--precision", choices=["mixed", "fp32"], default="mixed",
+    ap.add_argument("--precision", choices=["mixed", "fp64", "fp32"], default="mixed",
                     help="the timed solve: FP32 V-cycle inside FP64 refinement (default), "
                          "or everything in FP32 (its residual stalls near 1e-4 relative: "
                          "use --tol above that)")
@@ -237,13 +268,15 @@ def main():
         "metric": METRIC, "value": mean_s, "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mean_s * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f32", "data": "synthetic",
+        "dtype": {"mixed": "f32+f64", "fp64": "f64", "fp32": "f32"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": sh.name, "grid": [sh.nlon, sh.nlat, sh.nlev],
                    "unknowns": sh.n, "cycle": f"V({sh.nu_pre},{sh.nu_post})",
                    "tol": args.tol, "levels": st.levels, "iters": st.iters,
                    "hierarchy": "automatic" if args.levels == 0 else f"at most {args.levels} levels",
-                   "precision": ("FP32 V-cycle inside FP64 refinement"
-                                 if args.precision == "mixed" else "FP32 throughout"),
+                   "precision": {"mixed": "FP32 V-cycle inside FP64 refinement",
+                                 "fp64": "FP64 throughout",
+                                 "fp32": "FP32 throughout"}[args.precision],
                    "smoothing": (f"Chebyshev factors on [{smooth[0]:g}, {smooth[1]:g}]"
                                  if smooth else "omega 0.8 every sweep")},
         "median_s": statistics.median(times),
@@ -288,6 +321,8 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sh, st.iters, smooth)
+        if sh.n <= 1_000_000:
+            out["oracle_solve"] = oracle_solve(sh, args.tol, smooth, u_mixed.cpu().numpy())
     print(json.dumps(out), flush=True)
 
 

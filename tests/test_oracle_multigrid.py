@@ -119,8 +119,10 @@ def test_convergence_factor():
 
     Damped block-Jacobi bounds the smoothing factor per sweep from below
     (about 0.6-0.73, see the hierarchy module); V(1,1) on the small shell
-    and V(2,2) on a 70-level medium shell (reduced horizontally) measure
-    below 0.45 and 0.3."""
+    (constant omega, a one-sweep step) measures below 0.45. V(2,2) and V(2,3)
+    on a 70-level medium shell (reduced horizontally), with the default
+    per-sweep Chebyshev factors, must stay below 0.2 per cycle (measured:
+    at most 0.103 and 0.074)."""
     sh = shellgen.workload("shell64x32x16")
     L = build_hierarchy(sh, shellgen.alpha(sh))
     _, st = solve(L, shellgen.rhs(sh), Options(nu_pre=1, nu_post=1), tol=1e-11)
@@ -130,7 +132,10 @@ def test_convergence_factor():
     L2 = build_hierarchy(sh2, shellgen.alpha(sh2))
     _, st2 = solve(L2, shellgen.rhs(sh2), Options(), tol=1e-11, fixed_iters=8)
     rho2 = convergence_factors(st2["res_hist"])
-    assert rho2.max() < 0.3, rho2
+    assert rho2.max() < 0.2, rho2
+    _, st3 = solve(L2, shellgen.rhs(sh2), Options(nu_post=3), tol=1e-11, fixed_iters=8)
+    rho3 = convergence_factors(st3["res_hist"])
+    assert rho3.max() < 0.2, rho3
 
 
 def test_convergence_insensitive_to_vertical_geometry():
