@@ -210,6 +210,31 @@ struct NoLaneTable {
     __device__ __forceinline__ NoLaneTable(const T*, int, int, int) {}
 };
 
+// Two block sums with one barrier: *out_a = sum of a, *out_b = sum of b.
+template <typename T>
+__device__ __forceinline__ void block_sum2_to(T a, T b, T* out_a, T* out_b) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    __shared__ T red2[2][1024 / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red2[0][wave] = a;
+        red2[1][wave] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T ta = 0, tb = 0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) {
+            ta += red2[0][w];
+            tb += red2[1][w];
+        }
+        *out_a = ta;
+        *out_b = tb;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void block_sum_to(T v, T* out) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

@@ -55,15 +55,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __res
 // segments, one wavefront per row of the block's tile), in the precision TU
 // of the iterate (FP64; FP32 in the pure single-precision solve):
 //   unew = uin + e (HAS_E; written to uout), r = b - H unew (stored as TR),
-//   per-block partial sums of r^2 in FP64.
+//   per-block partial sums of r^2 in FP64, and of b^2 when partials_b is set.
 template <typename TU, typename TE, typename TR, int NZ, bool HAS_E, int R>
 __global__ __launch_bounds__(64 * R) void k_residual_update(
     LevelView<TU> L, const TU* __restrict__ bv, const TU* __restrict__ uin,
     const TE* __restrict__ e, TU* __restrict__ uout, TR* __restrict__ r,
-    double* __restrict__ partials, int wpr) {
+    double* __restrict__ partials, double* __restrict__ partials_b, int wpr) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     const Seg g = tiled_segment(int(logical_block()), wave, R, L.nI, L.nJ, wpr);
-    double acc = 0;
+    double acc = 0, accb = 0;
     {
         const Seg& nb = g;
         const NbB<TU> bu(nb);
@@ -89,11 +89,13 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
                       tab(L.Tth, kk * (nJ + 1) + nb.J + 1), uc, un(kk, bu.w, be.w),
                       un(kk, bu.e, be.e), un(kk, bu.s, be.s), un(kk, bu.n, be.n)) +
                 tab(L.Tr, kk * nJ + nb.J) * (uc - um) + tab(L.Tr, (kk + 1) * nJ + nb.J) * (uc - up);
-            const TU rv = ldb<TU>(layer(bv, kk, PU), bu.c) - h;
+            const TU bk = ldb<TU>(layer(bv, kk, PU), bu.c);
+            const TU rv = bk - h;
             if (k < nz && g.valid) {
                 if constexpr (HAS_E) stb<TU>(layer_w(uout, kk, PU), bu.c, uc);
                 stb<TR>(layer_w(r, kk, PR), br.c, TR(rv));
                 acc += double(rv) * double(rv);
+                accb += double(bk) * double(bk);
             }
             um = uc;
             uc = up;
@@ -102,22 +104,16 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
                 if (k % MG_RESIDUAL_SYNC == MG_RESIDUAL_SYNC - 1) __syncthreads();
         }
     }
-    block_sum_to(acc, partials + blockIdx.x);
+    if (partials_b) block_sum2_to(acc, accb, partials + blockIdx.x, partials_b + blockIdx.x);
+    else block_sum_to(acc, partials + blockIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_norm2_partials(const double* __restrict__ x,
-                                                           long long n,
-                                                           double* __restrict__ partials) {
-    double acc = 0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
-        acc += x[t] * x[t];
-    block_sum_to(acc, partials + blockIdx.x);
-}
-
+// Block c sums the c-th array of partials (arrays `stride` apart) into out[c].
 __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict__ p, int n,
+                                                       long long stride,
                                                        double* __restrict__ out) {
     __shared__ double red[1024];
+    p += blockIdx.x * stride;
     double acc = 0;
     for (int t = threadIdx.x; t < n; t += blockDim.x) acc += p[t];
     red[threadIdx.x] = acc;
@@ -126,7 +122,7 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* __restrict_
         if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Setup: M = alpha V on the finest level; counts alpha values that are not
@@ -245,14 +241,15 @@ void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
 
 template <typename TU, typename TE, typename TR>
 int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE* e, TU* uout,
-                    TR* r, double* partials, hipStream_t s) {
+                    TR* r, double* partials, double* partials_b, hipStream_t s) {
     const int wpr = segments_per_row(L.nI);
     const int nb = residual_update_blocks(L);
     const bool tall = residual_tile_rows(L.nI, L.nJ) == 16;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
 #define MG_RESIDUAL_LAUNCH(HE, R) \
-    k_residual_update<TU, TE, TR, NZ, HE, R><<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, wpr)
+    k_residual_update<TU, TE, TR, NZ, HE, R><<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, \
+                                                                  partials_b, wpr)
         if (tall) {
             if (e) MG_RESIDUAL_LAUNCH(true, 16); else MG_RESIDUAL_LAUNCH(false, 16);
         } else {
@@ -268,14 +265,9 @@ int residual_update_blocks(const LevelView<TU>& L) {
     return tiled_blocks(L.nJ, segments_per_row(L.nI), residual_tile_rows(L.nI, L.nJ));
 }
 
-int norm2_partials(const double* x, long long n, double* partials, hipStream_t s) {
-    const int nb = grid_stride_blocks(n);
-    k_norm2_partials<<<nb, kBlock, 0, s>>>(x, n, partials);
-    return nb;
-}
-
-void sum_partials(const double* partials, int n, double* out, hipStream_t s) {
-    k_sum_partials<<<1, 1024, 0, s>>>(partials, n, out);
+void sum_partials(const double* partials, int n, double* out, hipStream_t s, int count,
+                  long long stride) {
+    k_sum_partials<<<count, 1024, 0, s>>>(partials, n, stride, out);
 }
 
 int fine_mass(const LevelView<double>& L, const double* V, const double* alpha, double* M,
@@ -318,14 +310,14 @@ template void apply<double>(const LevelView<double>&, const double*, const doubl
                             hipStream_t);
 template int residual_update<double, float, float>(const LevelView<double>&, const double*,
                                                   const double*, const float*, double*,
-                                                  float*, double*, hipStream_t);
+                                                  float*, double*, double*, hipStream_t);
 template int residual_update<double, double, double>(const LevelView<double>&,
                                                      const double*, const double*,
                                                      const double*, double*, double*,
-                                                     double*, hipStream_t);
+                                                     double*, double*, hipStream_t);
 template int residual_update<float, float, float>(const LevelView<float>&, const float*,
                                                  const float*, const float*, float*, float*,
-                                                 double*, hipStream_t);
+                                                 double*, double*, hipStream_t);
 template int residual_update_blocks<double>(const LevelView<double>&);
 template int residual_update_blocks<float>(const LevelView<float>&);
 template void cast<double, float>(const double*, float*, long long, hipStream_t);

@@ -126,19 +126,19 @@ void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStrea
 // Refinement step on the finest level, in the iterate's precision TU (FP64;
 // FP32 in the pure single-precision solve):
 //   unew = uin + e (or uin when e == nullptr), written to uout if set;
-//   r = b - H unew, stored as TR; per-block partial sums of r^2 in FP64.
+//   r = b - H unew, stored as TR; per-block partial sums of r^2 in FP64,
+//   and of b^2 into partials_b when it is not null.
 // Returns the number of blocks (partials written).
 template <typename TU, typename TE, typename TR>
 int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE* e, TU* uout,
-                    TR* r, double* partials, hipStream_t s);
+                    TR* r, double* partials, double* partials_b, hipStream_t s);
 // Blocks (hence partial sums) residual_update launches for level L.
 template <typename TU>
 int residual_update_blocks(const LevelView<TU>& L);
 
-// Per-block partial sums of x^2.
-int norm2_partials(const double* x, long long n, double* partials, hipStream_t s);
-// out[0] = sum of partials[0..n) in a fixed order.
-void sum_partials(const double* partials, int n, double* out, hipStream_t s);
+// out[c] = sum of partials[c*stride + 0..n) in a fixed order, c < count.
+void sum_partials(const double* partials, int n, double* out, hipStream_t s, int count = 1,
+                  long long stride = 0);
 
 // Setup: M = alpha * V (fine level) and per-block counts of alpha values that
 // are not finite and > 0 (as FP64 partials).

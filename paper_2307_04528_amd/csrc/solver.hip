@@ -90,8 +90,8 @@ struct mg_handle {
     double* u_alt = nullptr;       // FP64 ping-pong partner of the caller's u
     float *u32a = nullptr, *u32b = nullptr, *b32 = nullptr;   // MG_PREC_FP32 solve
     double* partials = nullptr;
-    double* scalar = nullptr;      // device: reduced value
-    double* host_scalar = nullptr; // pinned host copy
+    double* scalar = nullptr;      // device: reduced values [2]
+    double* host_scalar = nullptr; // pinned host copy [2]
     hipEvent_t scalar_ready = nullptr;   // recorded after the copy to host_scalar
     int max_partials = 0;
     size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
@@ -468,7 +468,7 @@ mg_status vcycle_T(mg_handle* h, int l) {
 // is the event scalar_ready), and wait for it. Waiting on the event, not the
 // stream, lets work enqueued after the copy keep the GPU busy meanwhile.
 mg_status post_scalar(mg_handle* h) {
-    HIP_TRY(h, hipMemcpyAsync(h->host_scalar, h->scalar, sizeof(double),
+    HIP_TRY(h, hipMemcpyAsync(h->host_scalar, h->scalar, 2 * sizeof(double),
                               hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipEventRecord(h->scalar_ready, h->stream));
     return MG_OK;
@@ -485,28 +485,15 @@ mg_status sync_scalar(mg_handle* h, double* out) {
     return wait_scalar(h, out);
 }
 
-mg_status norm2(mg_handle* h, const double* x, long long n, double* out) {
-    int nb = 0;
-    {
-        Launch g(h, MG_K_OTHER, 0, double(n) * 8);
-        nb = mgk::norm2_partials(x, n, h->partials, h->stream);
-        mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
-    }
-    MG_TRY(check_launch(h, "norm2"));
-    double s2 = 0;
-    MG_TRY(sync_scalar(h, &s2));
-    *out = std::sqrt(s2);
-    return MG_OK;
-}
-
 // FP64 update + residual step; returns ||r||.
 // One refinement step with the iterate, b and H in precision U (FP64, or
 // FP32 in the pure single-precision solve) and the correction e and
 // residual r in the V-cycle's precision T.
-// Enqueues the step; its ||r||^2 reaches the host with post_scalar, read by
-// finish_step.
+// Enqueues the step; its ||r||^2 (and ||b||^2 with with_bnorm, summed in the
+// same pass) reaches the host with post_scalar, read by finish_step.
 template <typename T, typename U>
-mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r) {
+mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r,
+                      bool with_bnorm = false) {
     DevLevel& d = h->lv[0];
     const double bytes =
         double(d.n) * (3 * sizeof(U) + sizeof(T) + (e ? sizeof(T) + sizeof(U) : 0));
@@ -514,20 +501,25 @@ mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uou
     {
         Launch g(h, MG_K_RESIDUAL64, 0, bytes);
         nb = mgk::residual_update<U, T, T>(view<U>(d), b, uin, e, uout, r, h->partials,
+                                           with_bnorm ? h->partials + h->max_partials : nullptr,
                                            h->stream);
     }
     MG_TRY(check_launch(h, "residual_update"));
     {
-        Launch g(h, MG_K_OTHER, 0, double(nb) * 8);
-        mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
+        Launch g(h, MG_K_OTHER, 0, double(nb) * 8 * (with_bnorm ? 2 : 1));
+        mgk::sum_partials(h->partials, nb, h->scalar, h->stream, with_bnorm ? 2 : 1,
+                          h->max_partials);
     }
     return post_scalar(h);
 }
 
-mg_status finish_step(mg_handle* h, double* rnorm) {
+// ||r|| of the last step (and ||b|| into bnorm when given, for a step
+// enqueued with with_bnorm).
+mg_status finish_step(mg_handle* h, double* rnorm, double* bnorm = nullptr) {
     double s2 = 0;
     MG_TRY(wait_scalar(h, &s2));
     *rnorm = std::sqrt(s2);
+    if (bnorm) *bnorm = std::sqrt(h->host_scalar[1]);
     return MG_OK;
 }
 
@@ -544,7 +536,6 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     auto t0 = std::chrono::steady_clock::now();
     prof_reset(h);
     double bnorm = 0;
-    MG_TRY(norm2(h, b, d.n, &bnorm));
     const U* bU = nullptr;
     U *ucur = nullptr, *unext = nullptr;
     if constexpr (std::is_same<U, double>::value) {
@@ -570,12 +561,8 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
     T* r = transposed ? w.xbar : w.f;
     double rn = 0;
-    MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r)));
-    MG_TRY(finish_step(h, &rn));
-    std::vector<double> hist{rn};
-    int it = 0;
-    mg_status status = MG_OK;
-    if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
+    // (||b|| in the same pass)
+    MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r, true)));
     // enqueue one V-cycle on r; its correction e is what the next step adds
     auto cycle = [&](const T** e) -> mg_status {
         if (!transposed) {
@@ -588,7 +575,15 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
         }
         return MG_OK;
     };
+    // The first cycle is almost always needed: enqueue it before the wait
+    // (wasted only when u0 already meets the tolerance).
     const T* e_ahead = nullptr;   // a V-cycle already enqueued on the current r
+    if (h->opt.max_iters > 0) MG_TRY(cycle(&e_ahead));
+    MG_TRY(finish_step(h, &rn, &bnorm));
+    std::vector<double> hist{rn};
+    int it = 0;
+    mg_status status = MG_OK;
+    if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
     while (status == MG_OK) {
         if (rn <= tol * bnorm) break;
         if (it >= h->opt.max_iters) {
@@ -737,10 +732,10 @@ mg_status build(mg_handle* h, const double* alpha) {
     DevLevel& f = h->lv[0];
     h->max_partials = std::max({mgk::residual_update_blocks(view<double>(f)),
                                 mgk::blocks_for(f.plane), 8192});
-    MG_TRY(dalloc(h, &h->partials, size_t(h->max_partials)));
-    MG_TRY(dalloc(h, &h->scalar, 1));
+    MG_TRY(dalloc(h, &h->partials, 2 * size_t(h->max_partials)));
+    MG_TRY(dalloc(h, &h->scalar, 2));
     MG_TRY(dalloc(h, &h->u_alt, f.n));
-    HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, sizeof(double), hipHostMallocDefault));
+    HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, 2 * sizeof(double), hipHostMallocDefault));
     HIP_TRY(h, hipEventCreateWithFlags(&h->scalar_ready, hipEventDisableTiming));
     {
         int dev = 0, lds = 0;
