@@ -87,7 +87,8 @@ struct mg_handle {
     std::vector<DevLevel> lv;
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
-    double* u_alt = nullptr;       // FP64 ping-pong partner of the caller's u
+    double* u_alt = nullptr;       // FP64 iterate buffers beside the caller's u
+    double* u_alt2 = nullptr;
     float *u32a = nullptr, *u32b = nullptr, *b32 = nullptr;   // MG_PREC_FP32 solve
     double* partials = nullptr;
     double* scalar = nullptr;      // device: reduced values [2]
@@ -541,7 +542,6 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     if constexpr (std::is_same<U, double>::value) {
         bU = b;
         ucur = u;
-        unext = h->u_alt;
     } else {
         if (!h->b32) {
             MG_TRY(dalloc(h, &h->b32, d.n));
@@ -593,13 +593,21 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
         const T* e = e_ahead;
         if (!e) MG_TRY(cycle(&e));
         e_ahead = nullptr;
+        // the last contraction factor, carried forward to predict ||r||
+        const double rho = hist.size() >= 2 ? hist.back() / hist[hist.size() - 2] : 1.0;
+        if constexpr (std::is_same<U, double>::value) {
+            // The step predicted to be the last writes into the caller's u
+            // (when it does not read it), the others alternate between two
+            // buffers of their own: no copy at the end unless the prediction
+            // misses.
+            if (rn * std::min(rho, 1.0) <= tol * bnorm && ucur != u) unext = u;
+            else unext = ucur == h->u_alt ? h->u_alt2 : h->u_alt;
+        }
         MG_TRY((refine_step<T, U>(h, bU, ucur, e, unext, r)));
         // While the new norm travels to the host, keep the GPU busy with the
         // next V-cycle when the residual is predicted to stay well above the
-        // tolerance (the last contraction factor carried forward). The
-        // update itself waits for the norm, so a cycle enqueued in vain
-        // costs time only, never the result.
-        const double rho = hist.size() >= 2 ? hist.back() / hist[hist.size() - 2] : 1.0;
+        // tolerance. The update itself waits for the norm, so a cycle
+        // enqueued in vain costs time only, never the result.
         if (it + 1 < h->opt.max_iters && std::isfinite(rho) &&
             rn * std::min(rho, 1.0) > 3.0 * tol * bnorm)
             MG_TRY(cycle(&e_ahead));
@@ -735,6 +743,7 @@ mg_status build(mg_handle* h, const double* alpha) {
     MG_TRY(dalloc(h, &h->partials, 2 * size_t(h->max_partials)));
     MG_TRY(dalloc(h, &h->scalar, 2));
     MG_TRY(dalloc(h, &h->u_alt, f.n));
+    MG_TRY(dalloc(h, &h->u_alt2, f.n));
     HIP_TRY(h, hipHostMalloc((void**)&h->host_scalar, 2 * sizeof(double), hipHostMallocDefault));
     HIP_TRY(h, hipEventCreateWithFlags(&h->scalar_ready, hipEventDisableTiming));
     {
