@@ -24,7 +24,10 @@ __device__ __forceinline__ pair_t<T> ld2(gcptr base, uint32_t boff) {
 // two longitude children are adjacent, so each child row is one 2-value load;
 // the children rows, tables and transfer maps are wave-uniform. The x values
 // of the chunk's layers and the layers just outside it are loaded once.
-constexpr int kRestrictLayers = 4;
+#ifndef MG_RESTRICT_LAYERS
+#define MG_RESTRICT_LAYERS 4
+#endif
+constexpr int kRestrictLayers = MG_RESTRICT_LAYERS;
 template <typename T, bool HAS_X>
 __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, TransferView<T> X,
                                                          const T* __restrict__ f,
@@ -113,7 +116,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
 // of one chunk: the fine row's coarse rows and weights are wave-uniform, the
 // per-lane coarse columns are computed once, and the loads of the whole chunk
 // are independent and issued together.
-constexpr int kProlongLayers = 8;
+#ifndef MG_PROLONG_LAYERS
+#define MG_PROLONG_LAYERS 8
+#endif
+constexpr int kProlongLayers = MG_PROLONG_LAYERS;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, TransferView<T> X,
                                                         const T* __restrict__ xc,

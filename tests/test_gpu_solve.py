@@ -252,3 +252,52 @@ def test_vcycle_chebyshev_smoothing(nu):
         u_ref, _ = oracle_solution(sh)
         log(f"chebyshev mixed solve: {st.iters} iterations, fwd err {rel2(n(u), u_ref):.2e}")
         assert st.relres <= 1e-11 and rel2(n(u), u_ref) < 1e-8
+
+
+
+def solve_unchecked(S, b, tol):
+    """S.solve without raising on MG_ERR_NOT_CONVERGED (max_iters reached)."""
+    import ctypes as C
+    from paper_2307_04528_amd import _lib as Lb
+    from paper_2307_04528_amd.solver import SolveStats
+    S._sync_options()
+    bt = t(b)
+    u = S._empty()
+    u.zero_()
+    st = Lb.mg_stats()
+    s = Lb.lib().mg_solve(S._h, bt.data_ptr(), u.data_ptr(), float(tol), C.byref(st))
+    assert s in (0, 1), s
+    return n(u), SolveStats.from_c(st)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("sh", [SMALL, RAGGED], ids=lambda s: s.name)
+def test_solve_returns_last_iterate(sh, prec):
+    """The FP64 iterate moves between the caller's u and two buffers of the
+    library's; whichever update turns out last (predicted to be or not,
+    converged or stopped by max_iters), u must hold it. Tolerances just above
+    each predicted residual ||r_i||^2/||r_{i-1}|| make the prediction of the
+    last step hit or miss at every iteration count."""
+    a, b = shellgen.alpha(sh), shellgen.rhs(sh)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    bnorm = np.linalg.norm(b.ravel())
+    S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    _, st0 = solve_unchecked(S, b, 1e-12)
+    h = np.array(st0.res_hist)
+    tols = [h[i] ** 2 / h[i - 1] * 1.0001 / bnorm for i in range(1, len(h) - 1)]
+    cases = [dict(tol=tl) for tl in tols if tl > 1e-10]
+    cases += [dict(tol=1e-15, max_iters=k) for k in (1, 2, 3, 4)]
+    assert len(cases) >= 6
+    for c in cases:
+        Sc = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
+                        max_iters=c.get("max_iters", 100))
+        u, st = solve_unchecked(Sc, b, c["tol"])
+        host = np.linalg.norm((b - oracle.apply(L[0], u)).ravel()) / bnorm
+        log(f"last iterate {sh.name} {prec} {c}: iters {st.iters} relres {st.relres:.3e} "
+            f"host {host:.3e}")
+        # u is the iterate whose residual the solver reported
+        assert abs(host - st.relres) <= 1e-6 * st.relres + 1e-13, (c, host, st.relres)
+        if prec == "fp64":
+            ref, _ = oracle.solve(L, b, opt, fixed_iters=st.iters)
+            assert rel2(u, ref) < 1e-11, (c, st.iters, rel2(u, ref))
