@@ -42,6 +42,9 @@ namespace mgk {
 #ifndef MG_PAIRS64
 #define MG_PAIRS64 2
 #endif
+#ifndef MG_KEEPX32
+#define MG_KEEPX32 1
+#endif
 #ifndef MG_KEEPX64
 #define MG_KEEPX64 0
 #endif
@@ -238,7 +241,8 @@ struct StencilRaw {
 // would cost the second wavefront per SIMD).
 template <typename T>
 struct KeepX {
-    static constexpr bool value = std::is_same<T, float>::value ? true : (MG_KEEPX64 != 0);
+    static constexpr bool value = std::is_same<T, float>::value ? (MG_KEEPX32 != 0)
+                                                                : (MG_KEEPX64 != 0);
 };
 // Where a kept old iterate lives: in LDS (one 64-lane row per step of the
 // wavefront) instead of registers, which frees the registers for a fourth
