@@ -21,9 +21,16 @@ namespace mgk {
 // on the 1024x768x70 shell: 2.03 -> 1.70 GB fetched and 470 -> 448 us per
 // launch against 4-row tiles without the barrier.
 constexpr int kResidualTallBlocks = 512;
+#ifndef MG_RESIDUAL_TALL_ROWS
+#define MG_RESIDUAL_TALL_ROWS 16
+#endif
+constexpr int kResidualTallRows = MG_RESIDUAL_TALL_ROWS;
 
 static int residual_tile_rows(int nI, int nJ) {
-    return dev::tiled_blocks(nJ, dev::segments_per_row(nI), 16) >= kResidualTallBlocks ? 16 : 4;
+    return dev::tiled_blocks(nJ, dev::segments_per_row(nI), kResidualTallRows) >=
+                   kResidualTallBlocks
+               ? kResidualTallRows
+               : 4;
 }
 
 namespace {
@@ -244,14 +251,15 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
                     TR* r, double* partials, double* partials_b, hipStream_t s) {
     const int wpr = segments_per_row(L.nI);
     const int nb = residual_update_blocks(L);
-    const bool tall = residual_tile_rows(L.nI, L.nJ) == 16;
+    const bool tall = residual_tile_rows(L.nI, L.nJ) == kResidualTallRows;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
 #define MG_RESIDUAL_LAUNCH(HE, R) \
     k_residual_update<TU, TE, TR, NZ, HE, R><<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, \
                                                                   partials_b, wpr)
         if (tall) {
-            if (e) MG_RESIDUAL_LAUNCH(true, 16); else MG_RESIDUAL_LAUNCH(false, 16);
+            if (e) MG_RESIDUAL_LAUNCH(true, kResidualTallRows);
+            else MG_RESIDUAL_LAUNCH(false, kResidualTallRows);
         } else {
             if (e) MG_RESIDUAL_LAUNCH(true, 4); else MG_RESIDUAL_LAUNCH(false, 4);
         }
