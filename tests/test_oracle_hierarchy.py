@@ -133,3 +133,40 @@ def test_rows_merge_only_below_threshold():
     assert coarsen_rows(a, 1.0) == [(0, 1), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1),
                                     (6, 1), (7, 1)]
     assert coarsen_rows(np.ones(4), 2.0) == [(0, 2), (2, 2)]
+
+
+def test_aggregated_mass_cell_by_cell_by_containment():
+    """Coarse mass, cell by cell: each fine cell belongs to the coarse cell
+    whose longitude span and latitude edges contain its centre (geometry
+    only, none of the hierarchy's child maps or pairings), and the coarse
+    cell's M must be the sum of its fine cells' M. alpha varies along every
+    direction, so a wrong longitude pairing, row map or layer fails."""
+    sh = _shell(16, 8, nz=2)
+    nz, nj, ni = sh.shape
+    i, j, k = np.arange(ni), np.arange(nj), np.arange(nz)
+    alpha = 1.0 + i[None, None, :] + 10.0 * j[None, :, None] + 100.0 * k[:, None, None]
+    L = build_hierarchy(sh, alpha, levels=3)
+    assert _sizes(L) == [(16, 8), (8, 6), (4, 4)]
+    for fine, coarse in zip(L[:-1], L[1:]):
+        lon_centre = (np.arange(fine.nlon) + 0.5) * fine.dlam
+        I = np.floor(lon_centre / coarse.dlam).astype(int)
+        J = np.searchsorted(coarse.edges, fine.theta) - 1
+        expect = np.zeros(coarse.M.shape)
+        for jj in range(fine.nlat):
+            for ii in range(fine.nlon):
+                expect[:, J[jj], I[ii]] += fine.M[:, jj, ii]
+        np.testing.assert_allclose(coarse.M, expect, rtol=1e-14, atol=0)
+
+
+def test_aggregated_mass_worked_longitude_average():
+    """Worked by hand: with alpha = 1 + i (varying along longitude only),
+    coarse column I holds fine columns 2I and 2I+1, whose alpha are 2I+1 and
+    2I+2 over equal volumes, so the coarse mass over the coarse volume (the
+    volume-weighted mean alpha) is 2I + 1.5 on every row, merged or not;
+    one level further it is the mean over columns 4I..4I+3: 4I + 2.5."""
+    sh = _shell(16, 8, nz=2)
+    alpha = np.broadcast_to(1.0 + np.arange(16.0), sh.shape).copy()
+    L = build_hierarchy(sh, alpha, levels=3)
+    for l, want in ((1, 2.0 * np.arange(8) + 1.5), (2, 4.0 * np.arange(4) + 2.5)):
+        ratio = L[l].M / L[l].V[:, :, None]
+        np.testing.assert_allclose(ratio, np.broadcast_to(want, ratio.shape), rtol=1e-13)
