@@ -8,7 +8,15 @@ launch of the timed region is bracketed by HIP events on the solver's stream
 to give the dominant kernel's achieved bandwidth against the HBM roofline.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
-                    [--no-cpu-baseline] [--no-fp64]
+                    [--no-cpu-baseline] [--no-fp64] [--no-accuracy]
+
+After the timed solves, the oracle solves the same system on the host from
+u = 0 to the same tolerance (timed: cpu_baseline) and on to relres 1e-12;
+that solution is the reference for the forward errors of the GPU solves, and
+a sweep of tighter tolerances gives the time to a forward error of 1e-8.
+On workloads too large for the oracle (over 1e8 cells) the reference is the
+FP64 GPU solve to relres 1e-13, its residual recomputed on the host by the
+oracle's operator.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -74,36 +82,79 @@ def measured_traffic(workload, cls):
     return rec["bytes_per_launch"], rec["kernel"]
 
 
-def cpu_baseline(shell, iters_gpu, smooth):
-    """The oracle, untuned, on the host: one outer iteration (one V-cycle and
-    one FP64 residual) of the same workload, scaled by the GPU's iteration
-    count to a time-to-solution."""
-    import numpy as np
+def _oracle_setup(shell, smooth, threshold):
     import shellgen
     import oracle
     a, b = shellgen.alpha(shell), shellgen.rhs(shell)
-    t0 = time.perf_counter()
-    L = oracle.build_hierarchy(shell, a)
-    oracle.column_solve(L[0], np.zeros(shell.shape))   # pivots cached
-    t_setup = time.perf_counter() - t0
+    L = oracle.build_hierarchy(shell, a, threshold=threshold)
     opt = oracle.Options(nu_pre=shell.nu_pre, nu_post=shell.nu_post)
     opt.smooth_lo, opt.smooth_hi = smooth if smooth else (0.0, 0.0)
+    return L, b, opt
+
+
+def oracle_reference(shell, smooth, threshold, tol, tol_ref=1e-12, extra_iters=4):
+    """The oracle, untuned, on the host: its whole solve of the workload
+    from u = 0 to the bench tolerance, timed (wall clock, and the process's
+    CPU time, whose ratio is the number of cores it kept busy), then
+    continued from that iterate to relres tol_ref: the reference solution
+    the GPU solves' forward errors are measured against."""
+    import numpy as np
+    import oracle
     t0 = time.perf_counter()
-    r = b - oracle.apply(L[0], np.zeros(shell.shape))
-    u = oracle.vcycle(L, r, opt)
-    r = b - oracle.apply(L[0], u)
-    t_iter = time.perf_counter() - t0
-    rho = float(np.linalg.norm(r) / np.linalg.norm(b))
-    log(f"cpu oracle: setup {t_setup:.1f}s, one iteration {t_iter:.1f}s (rho {rho:.3f})")
-    return {"value": t_iter * iters_gpu, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"one outer iteration (V({shell.nu_pre},{shell.nu_post}) + FP64 "
-                       f"residual) of the numpy FP64 oracle on {shell.name}: "
-                       f"{t_iter:.2f} s, scaled by the GPU's {iters_gpu} iterations; "
-                       f"setup {t_setup:.1f} s not included"),
-            "per_iteration_s": t_iter}
+    L, b, opt = _oracle_setup(shell, smooth, threshold)
+    t_setup = time.perf_counter() - t0
+    w0, c0 = time.perf_counter(), time.process_time()
+    u, st = oracle.solve(L, b, opt, tol=tol)
+    wall, cpu = time.perf_counter() - w0, time.process_time() - c0
+    cores = max(1, round(cpu / wall)) if wall > 0 else 1
+    log(f"cpu oracle: setup {t_setup:.1f}s, solve to {tol:g} in {wall:.1f}s "
+        f"({st['iters']} iterations, relres {st['relres']:.2e}, cpu/wall {cpu / wall:.2f})")
+    t1 = time.perf_counter()
+    uref, st2 = oracle.solve(L, b, opt, tol=tol_ref, u0=u)
+    # a few more cycles: the residual stalls near FP64 rounding from here
+    # on, the iterate still converges, and the reference must be well ahead
+    # of the GPU solves it is compared with (which run the same cycle)
+    uref, st3 = oracle.solve(L, b, opt, u0=uref, fixed_iters=extra_iters)
+    log(f"cpu oracle: continued to relres {st2['relres']:.2e} "
+        f"(+{st2['iters']} iterations), then {extra_iters} more (relres {st3['relres']:.2e}), "
+        f"{time.perf_counter() - t1:.1f}s")
+    base = {"value": wall, "unit": "s", "cores": cores,
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": (f"the whole solve of {shell.name} by the numpy FP64 oracle from u = 0 to "
+                       f"relres {tol:g} (V({shell.nu_pre},{shell.nu_post}), {st['iters']} "
+                       f"iterations, relres {st['relres']:.2e}); setup {t_setup:.1f} s not "
+                       f"included; cores = its CPU time over wall time"),
+            "iters": st["iters"], "relres": st["relres"], "setup_s": t_setup}
+    ref = {"kind": "oracle", "relres": st3["relres"],
+           "iters": st["iters"] + st2["iters"] + st3["iters"]}
+    return uref, base, ref
 
 
-def oracle_solve(shell, tol, smooth, u_gpu):
+def gpu_reference(S64, shell, b, threshold, tol_ref=1e-13):
+    """Where the oracle's solve does not fit a bench run: the FP64 GPU solve
+    to relres tol_ref, with its residual recomputed on the host by the
+    oracle's operator (an independent FP64 check that it solves H u = b)."""
+    import numpy as np
+    import torch
+    import shellgen
+    import oracle
+    u = torch.zeros_like(b)
+    _, st = S64.solve(b, tol=tol_ref, out=u)
+    torch.cuda.synchronize()
+    L = oracle.build_hierarchy(shell, shellgen.alpha(shell), levels=1, threshold=threshold)
+    uh, bh = u.cpu().numpy(), b.cpu().numpy()
+    rel = float(np.linalg.norm(bh - oracle.apply(L[0], uh)) / np.linalg.norm(bh))
+    log(f"reference: FP64 GPU solve to {tol_ref:g} ({st.iters} iterations); "
+        f"oracle residual {rel:.2e}")
+    return u, {"kind": "FP64 GPU solve, residual checked by the oracle", "tol": tol_ref,
+               "iters": st.iters, "relres_oracle": rel}
+
+
+def fwd_err(u, uref):
+    return float((u - uref).norm() / uref.norm())
+
+
+def oracle_solve(shell, tol, smooth, threshold, u_gpu):
     """Small workloads (up to a million cells): the oracle's whole solve on
     the host, beside the GPU's. Reports its iterations, contraction factors,
     relative residual and time, the time of a sparse direct solve (scipy
@@ -113,10 +164,7 @@ def oracle_solve(shell, tol, smooth, u_gpu):
     import scipy.sparse.linalg as spla
     import shellgen
     import oracle
-    a, b = shellgen.alpha(shell), shellgen.rhs(shell)
-    L = oracle.build_hierarchy(shell, a)
-    opt = oracle.Options(nu_pre=shell.nu_pre, nu_post=shell.nu_post)
-    opt.smooth_lo, opt.smooth_hi = smooth if smooth else (0.0, 0.0)
+    L, b, opt = _oracle_setup(shell, smooth, threshold)
     t0 = time.perf_counter()
     u, st = oracle.solve(L, b, opt, tol=tol)
     t_solve = time.perf_counter() - t0
@@ -193,6 +241,12 @@ def main():
                     help="the timed solve: FP32 V-cycle inside FP64 refinement (default), "
                          "or everything in FP32 (its residual stalls near 1e-4 relative: "
                          "use --tol above that)")
+    ap.add_argument("--semi-threshold", type=float, default=2.0,
+                    help="latitude rows merge only where both rows' anisotropy is at most "
+                         "this (default 2, the library default)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the forward errors against a reference solution and the "
+                         "tolerance sweep")
     ap.add_argument("--timesteps", type=int, default=0, metavar="K",
                     help="also time K steps of a slowly varying sequence (alpha and b drift "
                          "by 2 %% per step): coefficient update plus a solve warm-started "
@@ -235,7 +289,7 @@ def main():
     # finest-level launch timed gives the per-kernel breakdown.
     S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
                           precision=args.precision, profile=3, smooth_interval=smooth,
-                          levels=args.levels)
+                          levels=args.levels, semi_threshold=args.semi_threshold)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     log(f"setup {t_setup * 1e3:.1f} ms")
@@ -278,7 +332,9 @@ def main():
                                  "fp64": "FP64 throughout",
                                  "fp32": "FP32 throughout"}[args.precision],
                    "smoothing": (f"Chebyshev factors on [{smooth[0]:g}, {smooth[1]:g}]"
-                                 if smooth else "omega 0.8 every sweep")},
+                                 if smooth else "omega 0.8 every sweep"),
+                   "semi_threshold": args.semi_threshold,
+                   "coarse_sweeps": S.option("coarse_sweeps"), "omega": S.option("omega")},
         "median_s": statistics.median(times),
         "relres": st.relres,
         "setup_s": t_setup,
@@ -304,25 +360,67 @@ def main():
     out["fine_level_kernels"] = {c: {"GBps": v["GBps"], "avg_ms": v["avg_ms"],
                                      "launches": v["launches"]} for c, v in kern.items()}
 
+    S64 = None
     if not args.no_fp64:
         S64 = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
                                 precision="fp64", profile=3, smooth_interval=smooth,
-                                levels=args.levels)
+                                levels=args.levels, semi_threshold=args.semi_threshold)
         times64, stats64, total64 = run(S64, args.steps, args.warmup, "fp64")
-        d = (u - u_mixed).norm() / u.norm()
+        u_fp64 = u.clone()
         out["fp64_solve_s"] = total64 / args.steps
         out["fp64_iters"] = stats64[-1].iters
         out["speedup_vs_fp64"] = (total64 / args.steps) / mean_s
-        out["mixed_vs_fp64_rel_diff"] = float(d)
-        S64.close()
+        out["mixed_vs_fp64_rel_diff"] = fwd_err(u_mixed, u_fp64)
 
     if args.timesteps > 0:
         out["timestep"] = timestep_run(S, sh, alpha, b, args.timesteps, args.tol)
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sh, st.iters, smooth)
-        if sh.n <= 1_000_000:
-            out["oracle_solve"] = oracle_solve(sh, args.tol, smooth, u_mixed.cpu().numpy())
+    # Accuracy: the forward error ||u - u_ref|| / ||u_ref|| of the timed
+    # solves against a reference solution of H u = b, and the loosest
+    # tolerance at which the timed solve's forward error is at most 1e-8.
+    uref = None
+    use_oracle = not args.no_cpu_baseline and sh.n <= 100_000_000
+    if use_oracle:
+        uref_np, base, ref = oracle_reference(sh, smooth, args.semi_threshold, args.tol)
+        out["cpu_baseline"] = base
+        uref = torch.from_numpy(uref_np).to(dev)
+        del uref_np
+    elif not args.no_accuracy:
+        S_ref = S64 or Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
+                                         precision="fp64", smooth_interval=smooth,
+                                         levels=args.levels,
+                                         semi_threshold=args.semi_threshold)
+        uref, ref = gpu_reference(S_ref, sh, b, args.semi_threshold)
+    if uref is not None:
+        acc = {"reference": ref, "fwd_err": fwd_err(u_mixed, uref)}
+        if S64 is not None:
+            acc["fwd_err_fp64"] = fwd_err(u_fp64, uref)
+        if not args.no_accuracy:
+            sweep = []
+            for tol in (1e-9, 1e-10, 1e-11, 1e-12):
+                ts = []
+                for _ in range(3):
+                    t1 = time.perf_counter()
+                    _, st_t = S.solve(b, tol=tol, out=u)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t1)
+                sweep.append({"tol": tol, "ms": statistics.median(ts) * 1e3,
+                              "iters": st_t.iters, "relres": st_t.relres,
+                              "fwd_err": fwd_err(u, uref)})
+            acc["tol_sweep"] = sweep
+            ok = [r for r in sweep if r["fwd_err"] <= 1e-8]
+            acc["to_fwd_err_1e-8"] = ok[0] if ok else None
+            log("forward errors: timed " + f"{acc['fwd_err']:.2e}" + "; " + ", ".join(
+                f"tol {r['tol']:g}: {r['ms']:.2f} ms, {r['iters']} it, {r['fwd_err']:.2e}"
+                for r in sweep))
+        out["accuracy"] = acc
+        del uref
+    if S64 is not None:
+        S64.close()
+
+    if use_oracle and sh.n <= 1_000_000:
+        out["oracle_solve"] = oracle_solve(sh, args.tol, smooth, args.semi_threshold,
+                                           u_mixed.cpu().numpy())
     print(json.dumps(out), flush=True)
 
 

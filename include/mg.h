@@ -71,6 +71,7 @@ typedef enum {
 /* Grid of the shell.
  * nlon, nlat : cells in longitude and latitude; both even, nlon >= 2.
  * nlev       : vertical layers, 1..MG_MAX_NLEV.
+ *              nlon * nlat * nlev < 2^29 (an FP64 field below 4 GiB).
  * radius     : inner radius R > 0 (the surface).
  * thickness  : shell depth D > 0.
  * stretch    : q > 0; layer depths dz_k = dz_0 q^k upward from the surface,
@@ -122,7 +123,18 @@ typedef struct {
  *                 their sweeps with the staged kernel: eight wavefronts
  *                 load a 64-column segment into LDS in one round trip, two
  *                 solve its columns from there (default 65536; 0 = never).
- *                 Same arithmetic either way; only the speed differs. */
+ *                 Same arithmetic either way; only the speed differs.
+ * stall_factor, stall_iters: stagnation guard of MG_PREC_MIXED. When
+ *                 stall_iters consecutive outer iterations each leave the
+ *                 residual norm above stall_factor times the previous one
+ *                 (the FP32 cycle no longer contracts), the solve continues
+ *                 from its current iterate with FP64 V-cycles and reports
+ *                 fell_back_fp64 = 1. Defaults 0.9 and 3; stall_iters = 0
+ *                 turns the guard off.
+ * graphs        : 1 (default): the forward V-cycle below the finest level
+ *                 is captured once as a HIP graph (at setup, again when
+ *                 options change) and replayed in every cycle; 0: every
+ *                 kernel is launched directly. Same kernels and results. */
 typedef struct {
     int32_t levels;
     int32_t nu_pre, nu_post, coarse_sweeps, max_iters;
@@ -132,6 +144,9 @@ typedef struct {
     int32_t profile;
     double smooth_lo, smooth_hi;
     int32_t staged_columns;
+    double stall_factor;
+    int32_t stall_iters;
+    int32_t graphs;
 } mg_options;
 
 /* Kernel classes reported by mg_stats when profiling. */
@@ -159,7 +174,12 @@ enum {
  * kern_ms[c], kern_launches[c], kern_bytes[c]: with options.profile, total
  *               event-timed milliseconds, launches and algorithmic bytes per
  *               kernel class; kern_fine_* the same restricted to the finest
- *               level. */
+ *               level.
+ * ms_vcycle   : device time of the V-cycles (HIP events around each one).
+ * ms_residual : device time of the refinement steps (update, residual and
+ *               its norm), timed the same way.
+ * fell_back_fp64: 1 if the stagnation guard switched a MG_PREC_MIXED solve
+ *               to FP64 V-cycles (see mg_options.stall_factor). */
 typedef struct {
     int32_t iters;
     double relres;
@@ -173,6 +193,8 @@ typedef struct {
     double kern_fine_ms[MG_NK];
     int64_t kern_fine_launches[MG_NK];
     double kern_fine_bytes[MG_NK];
+    double ms_vcycle, ms_residual;
+    int32_t fell_back_fp64;
 } mg_stats;
 
 typedef struct mg_handle mg_handle;
@@ -181,7 +203,8 @@ typedef struct mg_handle mg_handle;
  * max_iters 100, omega 0.8, semi_threshold 2, MG_PREC_MIXED, default stream,
  * no profiling, smoothing interval [1/3, 2] (the eigenvalues of H_z^{-1} H
  * on the modes the smoother must damp when merged latitude rows carry
- * anisotropy up to semi_threshold = 2: from 1/(1 + 2) to 2). */
+ * anisotropy up to semi_threshold = 2: from 1/(1 + 2) to 2), stagnation
+ * guard 0.9 over 3 iterations, graphs on. */
 void mg_options_default(mg_options* opts);
 
 /* Build the hierarchy for grid and coefficients (Sections 2.1-2.3):
@@ -194,7 +217,9 @@ void mg_options_default(mg_options* opts);
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs,
                    const mg_options* opts, mg_handle** out);
 
-/* Replace alpha (same grid, no reallocation): recomputes masses and pivots. */
+/* Replace alpha (same grid, no reallocation): recomputes masses, pivots and
+ * the coarsest level's solve matrix. alpha is checked first: a value that
+ * is not finite and > 0 gives MG_ERR_ARG and leaves the handle as it was. */
 mg_status mg_update_coeffs(mg_handle* h, const mg_coeffs* coeffs);
 
 /* Change the options of an existing handle; the hierarchy shape options

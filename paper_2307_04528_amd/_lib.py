@@ -39,7 +39,8 @@ class mg_options(C.Structure):
                 ("omega", C.c_double), ("semi_threshold", C.c_double),
                 ("precision", C.c_int32), ("stream", C.c_void_p), ("profile", C.c_int32),
                 ("smooth_lo", C.c_double), ("smooth_hi", C.c_double),
-                ("staged_columns", C.c_int32)]
+                ("staged_columns", C.c_int32), ("stall_factor", C.c_double),
+                ("stall_iters", C.c_int32), ("graphs", C.c_int32)]
 
 
 class mg_stats(C.Structure):
@@ -50,7 +51,9 @@ class mg_stats(C.Structure):
                 ("kern_bytes", C.c_double * MG_NK),
                 ("kern_fine_ms", C.c_double * MG_NK),
                 ("kern_fine_launches", C.c_int64 * MG_NK),
-                ("kern_fine_bytes", C.c_double * MG_NK)]
+                ("kern_fine_bytes", C.c_double * MG_NK),
+                ("ms_vcycle", C.c_double), ("ms_residual", C.c_double),
+                ("fell_back_fp64", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -89,9 +92,7 @@ EXPORTED = tuple(_SIGS)
 
 
 def load(path: str | None = None) -> C.CDLL:
-    # MGSHELL_LIB selects another build of the same library (e.g. a variant
-    # compiled with different tuning macros)
-    path = path or os.environ.get("MGSHELL_LIB") or LIB_PATH
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "

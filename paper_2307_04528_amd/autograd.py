@@ -18,21 +18,24 @@ class MGSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rhs: torch.Tensor, alpha: torch.Tensor, solver: Solver,
                 tol: float = 1e-8):
-        if alpha is not solver.alpha:
-            solver.update_alpha(alpha.detach().contiguous())
+        a = alpha.detach().contiguous()
+        if not solver.alpha_is_current(a):
+            solver.update_alpha(a)
         u, _ = solver.solve(rhs.detach().contiguous(), tol)
         ctx.solver = solver
         ctx.tol = tol
-        ctx.alpha = alpha
-        ctx.save_for_backward(u)
+        # saved, so that an in-place change of alpha before backward raises
+        ctx.save_for_backward(u, alpha)
         return u
 
     @staticmethod
     def backward(ctx, grad_u: torch.Tensor):
-        (u,) = ctx.saved_tensors
+        u, alpha = ctx.saved_tensors
         solver: Solver = ctx.solver
-        if ctx.alpha is not solver.alpha:
-            solver.update_alpha(ctx.alpha.detach().contiguous())
+        a = alpha.detach().contiguous()
+        if not solver.alpha_is_current(a):
+            # the solver has served another alpha since the forward solve
+            solver.update_alpha(a)
         lam, _ = solver.solve_adjoint(grad_u.contiguous(), ctx.tol)
         g_alpha = solver.grad_alpha(lam, u) if ctx.needs_input_grad[1] else None
         g_rhs = lam if ctx.needs_input_grad[0] else None

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmgshell.so")
 
-SOURCES = ["setup.cpp", "k_smooth.hip", "k_transfer.hip", "k_residual.hip", "k_dense.hip",
+SOURCES = ["setup.cpp", "k_smooth.hip", "k_sweep.hip", "k_transfer.hip", "k_residual.hip", "k_dense.hip",
            "solver.hip"]
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 

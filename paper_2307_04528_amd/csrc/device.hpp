@@ -114,6 +114,16 @@ __device__ __forceinline__ Seg tiled_segment(int b, int r, int R, int nI, int nJ
 }
 inline int tiled_blocks(int nJ, int wpr, int R) { return ((nJ + R - 1) / R) * wpr; }
 
+// Wavefront w of a block: pair w/2 of the block, bottom (even w) or top.
+struct PairOf {
+    int pair;
+    bool top;
+};
+__device__ __forceinline__ PairOf pair_of_wave() {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    return {wave >> 1, (wave & 1) != 0};
+}
+
 // The same offsets in bytes for element type T (a layer of any per-cell
 // array is < 4 GiB).
 template <typename T>

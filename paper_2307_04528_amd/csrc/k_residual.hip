@@ -8,23 +8,18 @@
 
 namespace mgk {
 
-#ifndef MG_RESIDUAL_SYNC
-#define MG_RESIDUAL_SYNC 4
-#endif
+constexpr int kResidualSync = 4;
 // A k_residual_update block has one wavefront per row of its tile of R
 // consecutive rows: R = 16 where that still gives at least
 // kResidualTallBlocks blocks, else R = 4 (small levels would leave CUs
-// idle). Every MG_RESIDUAL_SYNC layers the block's wavefronts meet at a
+// idle). Every kResidualSync layers the block's wavefronts meet at a
 // barrier: an XCD's L2 holds only a layer or two of all resident wavefronts'
 // rows, so the latitude neighbours a wavefront reads are L2 hits only while
 // the wavefronts that own those rows are at about the same layer. Measured
 // on the 1024x768x70 shell: 2.03 -> 1.70 GB fetched and 470 -> 448 us per
 // launch against 4-row tiles without the barrier.
 constexpr int kResidualTallBlocks = 512;
-#ifndef MG_RESIDUAL_TALL_ROWS
-#define MG_RESIDUAL_TALL_ROWS 16
-#endif
-constexpr int kResidualTallRows = MG_RESIDUAL_TALL_ROWS;
+constexpr int kResidualTallRows = 16;
 
 static int residual_tile_rows(int nI, int nJ) {
     return dev::tiled_blocks(nJ, dev::segments_per_row(nI), kResidualTallRows) >=
@@ -107,8 +102,7 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
             um = uc;
             uc = up;
             // keep the block's wavefronts within a few layers of each other
-            if constexpr (MG_RESIDUAL_SYNC > 0)
-                if (k % MG_RESIDUAL_SYNC == MG_RESIDUAL_SYNC - 1) __syncthreads();
+            if (k % kResidualSync == kResidualSync - 1) __syncthreads();
         }
     }
     if (partials_b) block_sum2_to(acc, accb, partials + blockIdx.x, partials_b + blockIdx.x);
@@ -146,7 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_fine_mass(LevelView<double> L,
         const int J = int((t - k * L.plane) / L.nI);
         const double a = alpha[t];
         if (!(a > 0.0) || !isfinite(a)) bad += 1.0;
-        M[t] = a * V[k * L.nJ + J];
+        if (M) M[t] = a * V[k * L.nJ + J];
     }
     block_sum_to(bad, partials + blockIdx.x);
 }

@@ -1,9 +1,13 @@
-// Block-Jacobi smoother (paper Eq. 1, Section 2.1) and its transpose.
+// Block-Jacobi smoother (paper Eq. 1, Section 2.1) on the small and the
+// coarsest levels, and its transpose (adjoint cycle).
 //
 // One sweep, with the vertical couplings in H_z solved exactly per column:
 //   x_new = (1 - omega) x + omega H_z^{-1} (f + sum_h T_h x_nb)
 // which equals x + omega H_z^{-1}(f - H x) since H = H_z + dH and dH holds
-// only the horizontal off-diagonals -T_h.
+// only the horizontal off-diagonals -T_h. Levels that fill the GPU sweep
+// with k_sweep (k_sweep.hip); the kernels here take the levels below
+// staged_columns (k_smooth_staged), the coarsest level (k_coarse_lds,
+// k_coarse_solve) and the transposed sweeps (k_smooth_T).
 //
 // Column solves use the twisted factorisation of H_z (pivots from setup). A
 // pair of wavefronts takes one row-aligned segment of up to 64 columns: the
@@ -11,99 +15,39 @@
 // going up, the top wavefront the layers above it going down; after one
 // exchange through LDS both know layer m, and each back-substitutes outward.
 // A wavefront thus walks half a column: the chain of dependent steps is half
-// as long as a one-sided Thomas solve, and everything the back-substitution
-// needs (forward values, couplings, the old iterate) fits in registers, so
-// the second pass reads nothing from memory.
+// as long as a one-sided Thomas solve.
 #include "device.hpp"
 
 namespace mgk {
 
-#ifndef MG_SMOOTH_WAVES32
-#define MG_SMOOTH_WAVES32 2
-#endif
-#ifndef MG_SMOOTH_WAVES64
-#define MG_SMOOTH_WAVES64 2
-#endif
-#ifndef MG_CHUNK32
-#define MG_CHUNK32 6
-#endif
-#ifndef MG_CHUNK64
-#define MG_CHUNK64 2
-#endif
-#ifndef MG_CHUNK_SMALL32
-#define MG_CHUNK_SMALL32 6
-#endif
-#ifndef MG_CHUNK_SMALL64
-#define MG_CHUNK_SMALL64 2
-#endif
-#ifndef MG_PAIRS32
-#define MG_PAIRS32 2
-#endif
-#ifndef MG_PAIRS64
-#define MG_PAIRS64 2
-#endif
-#ifndef MG_KEEPX32
-#define MG_KEEPX32 1
-#endif
-#ifndef MG_KEEPX64
-#define MG_KEEPX64 0
-#endif
-#ifndef MG_RAW32
-#define MG_RAW32 0
-#endif
-#ifndef MG_XLDS32
-#define MG_XLDS32 0
-#endif
-#ifndef MG_RAW64
-#define MG_RAW64 1
-#endif
-#ifndef MG_LANE_TABLES32
-#define MG_LANE_TABLES32 1
-#endif
-#ifndef MG_LANE_TABLES64
-#define MG_LANE_TABLES64 0
-#endif
-
 namespace {
 using namespace dev;
 
-// Occupancy target (waves per SIMD): caps the registers of a column kernel.
-template <typename T>
-struct ColumnWaves {
-    static constexpr int value = std::is_same<T, float>::value ? MG_SMOOTH_WAVES32
-                                                                : MG_SMOOTH_WAVES64;
-};
-// Layers per prefetch chunk on levels large enough to fill the GPU, and on
-// the smaller levels (where the per-column latency chain sets the time).
+// Occupancy target of the transposed sweep (waves per SIMD): caps its
+// registers.
+constexpr int kColumnWaves = 2;
+// Layers per prefetch chunk of the column kernels here.
 template <typename T>
 struct ChunkDepth {
-    static constexpr int value = std::is_same<T, float>::value ? MG_CHUNK32 : MG_CHUNK64;
-    static constexpr int small =
-        std::is_same<T, float>::value ? MG_CHUNK_SMALL32 : MG_CHUNK_SMALL64;
+    static constexpr int value = std::is_same<T, float>::value ? 6 : 2;
 };
-// Wavefront pairs per block of the sweep kernels (the pair's exchange is a
-// block barrier, so fewer pairs per block couple fewer columns).
-template <typename T>
-struct PairsPerBlock {
-    static constexpr int value = std::is_same<T, float>::value ? MG_PAIRS32 : MG_PAIRS64;
-};
+// Wavefront pairs per block of the transposed sweep (the pair's exchange is
+// a block barrier, so fewer pairs per block couple fewer columns).
+constexpr int kPairsPerBlock = 2;
 
 // Prefetch the raw loads of a chunk (FP64: the loads then stay in flight
 // while the previous chunk is solved) or combine them into the chunk's
-// right-hand sides at fetch time (FP32: fewer registers, more wavefronts per
-// SIMD, which hides the latency better at this size). Both measured.
+// right-hand sides at fetch time (FP32: fewer registers).
 template <typename T>
 struct RawPrefetch {
-    static constexpr bool value = std::is_same<T, float>::value ? (MG_RAW32 != 0)
-                                                                : (MG_RAW64 != 0);
+    static constexpr bool value = !std::is_same<T, float>::value;
 };
 
 // Read a wavefront's row couplings from lane tables (FP32) or with scalar
 // loads (FP64: the tables' registers would spill the x sweep).
 template <typename T>
 struct LaneTables {
-    static constexpr bool value = std::is_same<T, float>::value ? (MG_LANE_TABLES32 != 0)
-                                                                : (MG_LANE_TABLES64 != 0);
+    static constexpr bool value = std::is_same<T, float>::value;
 };
 
 // Steps of one wavefront of a pair for the layer bucket NZ.
@@ -237,19 +181,10 @@ struct StencilRaw {
 };
 
 // Keep the old iterate of a column in registers between the two passes
-// (FP32), or load it again in the back-substitution (FP64, where keeping it
-// would cost the second wavefront per SIMD).
+// (FP32), or load it again in the back-substitution (FP64).
 template <typename T>
 struct KeepX {
-    static constexpr bool value = std::is_same<T, float>::value ? (MG_KEEPX32 != 0)
-                                                                : (MG_KEEPX64 != 0);
-};
-// Where a kept old iterate lives: in LDS (one 64-lane row per step of the
-// wavefront) instead of registers, which frees the registers for a fourth
-// wavefront per SIMD (FP32, up to 72 layers: 16 wavefronts need 144 KiB).
-template <typename T, int NZ>
-struct KeepXInLds {
-    static constexpr bool value = std::is_same<T, float>::value && NZ <= 72 && MG_XLDS32 != 0;
+    static constexpr bool value = std::is_same<T, float>::value;
 };
 
 // One sweep of the segment's columns (see the file comment); HAS_X false:
@@ -257,15 +192,13 @@ struct KeepXInLds {
 template <typename T, int NZ, int D, bool HAS_X>
 __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f, const T* xin,
                                               T* xout, T omega, const Seg& g, bool top,
-                                              T* xch, T* xlds) {
+                                              T* xch) {
     const NbB<T> b(g);
     const int nJ = L.nJ, J = g.J;
     const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
     const T keep = T(1) - omega;
     constexpr bool KX = HAS_X && KeepX<T>::value;
-    constexpr bool XL = KX && KeepXInLds<T, NZ>::value;
-    const int lane = int(threadIdx.x & 63u);
-    T xk[KX && !XL ? padded_steps<NZ, D>() : 1];
+    T xk[KX ? padded_steps<NZ, D>() : 1];
     auto fetch = [&](int, int kk) {
         StencilRaw<T> r{};
         r.f = ldb<T>(layer(f, kk, Pb), b.c);
@@ -296,8 +229,7 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
                 s += tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
                      tab(L.Tth, kk * (nJ + 1) + J) * r.s +
                      tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
-            if constexpr (XL) xlds[t * 64 + lane] = r.c;
-            else if constexpr (KX) xk[t] = r.c;
+            if constexpr (KX) xk[t] = r.c;
         }
         return s;
     };
@@ -310,41 +242,12 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
     auto bload = [&](int kk) -> T { return ldb<T>(layer(xin, kk, Pb), b.c); };
     auto sink = [&](int t, int kk, T z, T e) {
         T out = omega * z;
-        if constexpr (XL) out += keep * xlds[t * 64 + lane];
-        else if constexpr (KX) out += keep * xk[t];
+        if constexpr (KX) out += keep * xk[t];
         else if constexpr (HAS_X) out += keep * e;
         if (g.valid) stb<T>(layer_w(xout, kk, Pb), b.c, out);
     };
     twisted_column<T, NZ, D, HAS_X && !KX>(L.nz, top, xch, fetch, comb, inv, cpl, fsink, bload,
                                             sink);
-}
-
-// Wavefront w of a block: pair w/2 of the block, bottom (even w) or top.
-struct PairOf {
-    int pair;
-    bool top;
-};
-__device__ __forceinline__ PairOf pair_of_wave() {
-    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    return {wave >> 1, (wave & 1) != 0};
-}
-
-// LARGE: the level has at least kSmallLevelColumns columns. The flag changes
-// no code; it keeps the sweeps of the bandwidth-bound large levels a symbol
-// of their own, apart from the latency-bound small levels, in profiles.
-template <typename T, int NZ, int D, bool HAS_X, bool LARGE>
-__global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
-__attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
-void k_smooth(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
-              T* __restrict__ xout, T omega, int wpr) {
-    constexpr int PB = PairsPerBlock<T>::value;
-    __shared__ T xch[PB][256];
-    constexpr bool XL = HAS_X && KeepX<T>::value && KeepXInLds<T, NZ>::value;
-    __shared__ T xlds[XL ? 2 * PB : 1][XL ? padded_steps<NZ, D>() * 64 : 1];
-    const PairOf p = pair_of_wave();
-    const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
-    sweep_segment<T, NZ, D, HAS_X>(L, f, xin, xout, omega, g, p.top, xch[p.pair],
-                                   xlds[XL ? 2 * p.pair + int(p.top) : 0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,10 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
                                                        T* xa, T* xb, T omega, int sweeps,
                                                        int wpr) {
     __shared__ T xch[kBlock / 128][256];
-    constexpr bool XL = KeepX<T>::value && KeepXInLds<T, NZ>::value;
-    __shared__ T xlds[XL ? kBlock / 64 : 1][XL ? padded_steps<NZ, D>() * 64 : 1];
     const PairOf p = pair_of_wave();
-    T* xl = xlds[XL ? 2 * p.pair + int(p.top) : 0];
     const int nseg = L.nJ * wpr;
     for (int s = 0; s < sweeps; ++s) {
         T* xout = (s & 1) ? xb : xa;
@@ -515,10 +415,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
         for (int s0 = 0; s0 < nseg; s0 += kBlock / 128) {
             const Seg g = segment(s0 + p.pair, L.nI, L.nJ, wpr);
             if (s == 0)
-                sweep_segment<T, NZ, D, false>(L, f, nullptr, xout, omega, g, p.top, xch[p.pair],
-                                               xl);
+                sweep_segment<T, NZ, D, false>(L, f, nullptr, xout, omega, g, p.top,
+                                               xch[p.pair]);
             else
-                sweep_segment<T, NZ, D, true>(L, f, xin, xout, omega, g, p.top, xch[p.pair], xl);
+                sweep_segment<T, NZ, D, true>(L, f, xin, xout, omega, g, p.top, xch[p.pair]);
             __syncthreads();
         }
     }
@@ -562,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     const int col = p.pair * 64 + int(threadIdx.x & 63u);
     const bool active = col < plane;
     const Nb b = neighbours<false>(active ? uint32_t(col) : 0u, L.nI, nJ);
-    constexpr int D = ChunkDepth<T>::small;
+    constexpr int D = ChunkDepth<T>::value;
     constexpr int NP = padded_steps<NZ, D>();
     const T keep = T(1) - omega;
     const int m = nz >> 1, nown = p.top ? nz - m : m;   // layers this wavefront writes
@@ -621,12 +521,12 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
 //   xb' = HAS_Z ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout)
 //   z = H_z^{-1} xb';  fb = (ACC ? fb : 0) + omega z;  zout = z (if set)
 template <typename T, int NZ, int D, bool HAS_Z, bool ACC>
-__global__ __launch_bounds__(128 * PairsPerBlock<T>::value)
-__attribute__((amdgpu_waves_per_eu(ColumnWaves<T>::value)))
+__global__ __launch_bounds__(128 * kPairsPerBlock)
+__attribute__((amdgpu_waves_per_eu(kColumnWaves)))
 void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
                 T* xbout,  // may alias xb
                 T* __restrict__ zout, T* __restrict__ fb, T omega_prev, T omega, int wpr) {
-    constexpr int PB = PairsPerBlock<T>::value;
+    constexpr int PB = kPairsPerBlock;
     __shared__ T xch[PB][256];
     const PairOf p = pair_of_wave();
     const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
@@ -696,7 +596,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_stencil(LevelView<T> L,
 // Blocks of PB wavefront pairs (row tiles of PB rows) covering every segment.
 template <typename T>
 inline int pair_blocks(const int nJ, const int wpr) {
-    return tiled_blocks(nJ, wpr, PairsPerBlock<T>::value);
+    return tiled_blocks(nJ, wpr, kPairsPerBlock);
 }
 
 }  // namespace
@@ -741,22 +641,7 @@ template <typename T>
 void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
             long long staged_columns, hipStream_t s) {
     if (launch_staged<T>(L, f, xin, xout, omega, staged_columns, s)) return;
-    const int wpr = segments_per_row(L.nI);
-    const int nb = pair_blocks<T>(L.nJ, wpr);
-    constexpr int threads = 128 * PairsPerBlock<T>::value;
-    const bool small = L.plane < kSmallLevelColumns;
-    with_nz(L.nz, [&](auto nzc) {
-        constexpr int NZ = decltype(nzc)::value;
-        constexpr int DB = ChunkDepth<T>::value, DS = ChunkDepth<T>::small;
-#define MG_SMOOTH_LAUNCH(D, HX, LG) \
-    k_smooth<T, NZ, D, HX, LG><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr)
-        if (small) {
-            if (xin) MG_SMOOTH_LAUNCH(DS, true, false); else MG_SMOOTH_LAUNCH(DS, false, false);
-        } else {
-            if (xin) MG_SMOOTH_LAUNCH(DB, true, true); else MG_SMOOTH_LAUNCH(DB, false, true);
-        }
-#undef MG_SMOOTH_LAUNCH
-    });
+    sweep<T>(L, f, xin, xout, omega, s);
 }
 
 // Launch k_coarse_lds<T, NZ, UNIT> on `blocks` blocks; false if the level
@@ -790,7 +675,7 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
     const int wpr = segments_per_row(L.nI);
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
-        k_coarse_solve<T, NZ, ChunkDepth<T>::small><<<1, kBlock, 0, s>>>(L, f, xa, xb, omega,
+        k_coarse_solve<T, NZ, ChunkDepth<T>::value><<<1, kBlock, 0, s>>>(L, f, xa, xb, omega,
                                                                          sweeps, wpr);
     });
     return (sweeps & 1) ? 0 : 1;
@@ -801,7 +686,7 @@ void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout
                       T* fb, T omega_prev, T omega, bool accumulate, hipStream_t s) {
     const int wpr = segments_per_row(L.nI);
     const int nb = pair_blocks<T>(L.nJ, wpr);
-    constexpr int threads = 128 * PairsPerBlock<T>::value;
+    constexpr int threads = 128 * kPairsPerBlock;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int D = ChunkDepth<T>::value;

@@ -28,12 +28,8 @@ __device__ __forceinline__ pair_t<T> ld2(gcptr base, uint32_t boff) {
 // workloads: 185 us per finest-level launch on 1024x768x70, against 199 us
 // with 4 layers, 190 with 6 and 212 with 8); 4 elsewhere (smaller levels
 // need the parallelism of more chunks, and FP64 solves were 5 % slower with 7).
-#ifndef MG_RESTRICT_LAYERS
-#define MG_RESTRICT_LAYERS 4
-#endif
-#ifndef MG_RESTRICT_LAYERS_LARGE32
-#define MG_RESTRICT_LAYERS_LARGE32 7
-#endif
+constexpr int kRestrictLayers = 4;
+constexpr int kRestrictLayersLarge32 = 7;
 template <typename T, bool HAS_X, int DL>
 __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, TransferView<T> X,
                                                          const T* __restrict__ f,
@@ -122,10 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
 // per-lane coarse columns are computed once, and the loads of the whole chunk
 // are independent and issued together.
 // (8: 98 us on 1024x768x70, against 115 us with 4 or 16 layers)
-#ifndef MG_PROLONG_LAYERS
-#define MG_PROLONG_LAYERS 8
-#endif
-constexpr int kProlongLayers = MG_PROLONG_LAYERS;
+constexpr int kProlongLayers = 8;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, TransferView<T> X,
                                                         const T* __restrict__ xc,
@@ -231,8 +224,8 @@ void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T*
     const int wprc = segments_per_row(X.nIc);
     const int nsegc = X.nJc * wprc;
     constexpr int waves = kBlock / 64;
-    constexpr int DLS = MG_RESTRICT_LAYERS;
-    constexpr int DLL = std::is_same<T, float>::value ? MG_RESTRICT_LAYERS_LARGE32 : DLS;
+    constexpr int DLS = kRestrictLayers;
+    constexpr int DLL = std::is_same<T, float>::value ? kRestrictLayersLarge32 : DLS;
     if (F.plane >= kSmallLevelColumns) {
         const int units = nsegc * ((F.nz + DLL - 1) / DLL);
         const int nb = (units + waves - 1) / waves;

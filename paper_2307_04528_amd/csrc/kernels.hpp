@@ -6,6 +6,19 @@
 
 namespace mgk {
 
+// The couplings one step of a column sweep needs, in the order a wavefront
+// walks its half of the column: record t of direction dir (0: upward from
+// layer 0, 1: downward from layer nz-1) and row J is that of layer
+// k = dir ? nz-1-t : t (clamped to [0, nz-1]): Tlam[k][J], Tth[k][J],
+// Tth[k][J+1], and tc, the vertical coupling to the next layer in that
+// direction (Tr[k+1][J] upward, Tr[k][J] downward). Table layout
+// [dir][J][t], kStepStride records per row.
+template <typename T>
+struct alignas(4 * sizeof(T)) StepCoef {
+    T tl, ts, tn, tc;
+};
+constexpr int kStepStride = 72;
+
 // Geometry and operator data of one level, in the precision T of the kernels
 // that read it. Fields are [k][J][i] with i fastest; plane = nI*nJ.
 template <typename T>
@@ -17,6 +30,7 @@ struct LevelView {
     const T* Tr;     // [nz+1][nJ], face F below layer F
     const T* M;      // [nz][plane] mass sum(alpha V)
     const T* invp;   // [nz][plane] inverse pivots of the twisted factorisation of H_z
+    const StepCoef<T>* sc;   // [2][nJ][kStepStride] step records (see StepCoef)
 };
 
 // Maps between a fine level and the next coarser one.
@@ -49,6 +63,11 @@ void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s);
 template <typename T>
 void smooth(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega,
             long long staged_columns, hipStream_t s);
+
+// The same sweep with the kernel for levels that fill the GPU (k_sweep.hip),
+// which smooth() uses on every level it does not stage.
+template <typename T>
+void sweep(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, hipStream_t s);
 
 // The whole coarsest-level solve in one launch (one block): `sweeps` sweeps
 // from zero, ping-ponging between xa and xb. Returns 0 if the result is in
@@ -140,8 +159,9 @@ int residual_update_blocks(const LevelView<TU>& L);
 void sum_partials(const double* partials, int n, double* out, hipStream_t s, int count = 1,
                   long long stride = 0);
 
-// Setup: M = alpha * V (fine level) and per-block counts of alpha values that
-// are not finite and > 0 (as FP64 partials).
+// Setup: M = alpha * V (fine level; not written when M is null) and
+// per-block counts of alpha values that are not finite and > 0 (as FP64
+// partials).
 int fine_mass(const LevelView<double>& L, const double* V, const double* alpha,
               double* M, double* partials, hipStream_t s);
 // Setup: row-sum pivots of the twisted factorisation of H_z (eliminated from

@@ -184,14 +184,17 @@ std::string validate(const mg_grid& g, const mg_options& o) {
         !std::isfinite(g.radius) || !std::isfinite(g.thickness) ||
         !std::isfinite(g.stretch) || !std::isfinite(g.K))
         return "radius, thickness, stretch and K must be finite and > 0";
-    if (double(g.nlon) * g.nlat * g.nlev > 4.0e9)
-        return "grid too large (more than 4e9 cells)";
+    if (double(g.nlon) * g.nlat * g.nlev >= 536870912.0)
+        return "grid too large (2^29 cells or more: an FP64 field must stay below 4 GiB)";
     if (o.levels < 0 || o.levels > MG_MAX_LEVELS) return "levels must be in 0..32";
     if (o.nu_pre < 1 || o.nu_post < 0 || o.nu_pre > 16 || o.nu_post > 16)
         return "need 1 <= nu_pre <= 16 and 0 <= nu_post <= 16";
     if (o.coarse_sweeps < 1 || o.coarse_sweeps > 1000) return "coarse_sweeps must be in 1..1000";
     if (o.max_iters < 0 || o.max_iters > MG_HIST - 1) return "max_iters must be in 0..127";
     if (!(o.omega > 0 && o.omega < 2)) return "omega must be in (0, 2)";
+    if (!(o.stall_factor > 0) || !std::isfinite(o.stall_factor) || o.stall_iters < 0)
+        return "stall_factor must be finite and > 0, stall_iters >= 0";
+    if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
     if (!(o.semi_threshold > 0) || !std::isfinite(o.semi_threshold))
         return "semi_threshold must be finite and > 0";
     if (o.precision != MG_PREC_MIXED && o.precision != MG_PREC_FP64 &&

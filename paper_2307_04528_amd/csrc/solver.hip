@@ -47,6 +47,8 @@ struct DevLevel {
     float *Tlam32 = nullptr, *Tth32 = nullptr, *Tr32 = nullptr;
     double *M64 = nullptr, *invp64 = nullptr;
     float *M32 = nullptr, *invp32 = nullptr;
+    mgk::StepCoef<double>* sc64 = nullptr;
+    mgk::StepCoef<float>* sc32 = nullptr;
     // to the next coarser level
     int *crow_of = nullptr, *prow = nullptr;
     double* pw64 = nullptr;
@@ -96,10 +98,23 @@ struct mg_handle {
     hipEvent_t scalar_ready = nullptr;   // recorded after the copy to host_scalar
     int max_partials = 0;
     size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
+    int device = 0;                // the GPU the handle lives on
+    bool no_events = false;        // record no HIP events (during graph capture)
     bool have32 = false, have64 = false;
     DenseCoarse dense;
+    // The V-cycle below the finest level (levels 1..L-1), per precision,
+    // captured once as a HIP graph and replayed in every forward cycle.
+    struct CoarseGraph {
+        hipGraphExec_t exec = nullptr;
+        void* result = nullptr;       // the level-1 buffer the cycle leaves its result in
+        double bytes = 0;             // its algorithmic bytes
+        bool dense_valid = false;     // the coarsest route it was captured with
+    } g32, g64;
+    hipStream_t cap_stream = nullptr; // private stream the graphs are captured on
+    bool capturing = false;
     std::string err;
     std::vector<ProfRec> recs;
+    std::vector<ProfRec> phases;   // cls 0: a V-cycle, 1: a refinement step
     std::vector<hipEvent_t> events;
     size_t next_event = 0;
     double alg_bytes = 0;
@@ -148,6 +163,26 @@ mg_status dalloc(mg_handle* h, T** p, size_t count) {
     return MG_OK;
 }
 
+// The step records of a level's column sweeps (mgk::StepCoef): for each
+// direction and row, the couplings of the layers in the order a wavefront
+// of a twisted pair walks them.
+template <typename T>
+std::vector<mgk::StepCoef<T>> step_table(const mgs::Level& s) {
+    const int nJ = s.nJ, nz = s.nz;
+    std::vector<mgk::StepCoef<T>> tab(size_t(2) * nJ * mgk::kStepStride);
+    for (int dir = 0; dir < 2; ++dir)
+        for (int J = 0; J < nJ; ++J)
+            for (int t = 0; t < mgk::kStepStride; ++t) {
+                const int k = std::min(std::max(dir ? nz - 1 - t : t, 0), nz - 1);
+                mgk::StepCoef<T>& q = tab[(size_t(dir) * nJ + J) * mgk::kStepStride + t];
+                q.tl = T(s.Tlam[size_t(k) * nJ + J]);
+                q.ts = T(s.Tth[size_t(k) * (nJ + 1) + J]);
+                q.tn = T(s.Tth[size_t(k) * (nJ + 1) + J + 1]);
+                q.tc = T(s.Tr[size_t(dir ? k : k + 1) * nJ + J]);
+            }
+    return tab;
+}
+
 template <typename T, typename S>
 mg_status upload(mg_handle* h, T** dst, const std::vector<S>& src) {
     MG_TRY(dalloc(h, dst, src.size()));
@@ -164,11 +199,11 @@ mgk::LevelView<T> view(const DevLevel& d);
 
 template <>
 mgk::LevelView<float> view<float>(const DevLevel& d) {
-    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam32, d.Tth32, d.Tr32, d.M32, d.invp32};
+    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam32, d.Tth32, d.Tr32, d.M32, d.invp32, d.sc32};
 }
 template <>
 mgk::LevelView<double> view<double>(const DevLevel& d) {
-    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam64, d.Tth64, d.Tr64, d.M64, d.invp64};
+    return {d.nI, d.nJ, d.nz, d.plane, d.Tlam64, d.Tth64, d.Tr64, d.M64, d.invp64, d.sc64};
 }
 
 template <typename T>
@@ -217,6 +252,7 @@ mg_status ensure_work(mg_handle* h) {
 
 // --- profiling ----------------------------------------------------------------
 hipEvent_t next_event(mg_handle* h) {
+    if (h->no_events) return nullptr;
     if (h->next_event == h->events.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
@@ -255,12 +291,41 @@ struct Launch {
 
 void prof_reset(mg_handle* h) {
     h->recs.clear();
+    h->phases.clear();
     h->next_event = 0;
     h->alg_bytes = 0;
 }
 
+// Events around one phase of the outer loop (a V-cycle or a refinement
+// step), summed into mg_stats.ms_vcycle / ms_residual.
+struct Phase {
+    mg_handle* h;
+    ProfRec rec{};
+    bool on = false;
+    Phase(mg_handle* hh, int kind) : h(hh) {
+        rec.cls = kind;
+        rec.a = next_event(h);
+        rec.b = next_event(h);
+        if (rec.a && rec.b) {
+            on = true;
+            (void)hipEventRecord(rec.a, h->stream);
+        }
+    }
+    ~Phase() {
+        if (!on) return;
+        (void)hipEventRecord(rec.b, h->stream);
+        h->phases.push_back(rec);
+    }
+};
+
 void prof_collect(mg_handle* h, mg_stats* st) {
     if (!st) return;
+    st->ms_vcycle = st->ms_residual = 0;
+    for (const ProfRec& r : h->phases) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        (r.cls == 0 ? st->ms_vcycle : st->ms_residual) += ms;
+    }
     for (int c = 0; c < MG_NK; ++c) {
         st->kern_ms[c] = st->kern_bytes[c] = st->kern_fine_ms[c] = st->kern_fine_bytes[c] = 0;
         st->kern_launches[c] = st->kern_fine_launches[c] = 0;
@@ -321,12 +386,26 @@ mg_status op_prolong(mg_handle* h, int l, const T* xc, T* x) {
     return check_launch(h, "prolong_add");
 }
 
+template <typename T>
+mg_handle::CoarseGraph& coarse_graph(mg_handle* h) {
+    return std::is_same<T, float>::value ? h->g32 : h->g64;
+}
+
 // One V-cycle from zero on level l; returns the buffer holding the result.
 template <typename T>
 mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     DevLevel& d = h->lv[l];
     Work<T>& w = work<T>(d);
     const int last = int(h->lv.size()) - 1;
+    if (l == 1 && !h->capturing && h->opt.profile != 2) {
+        mg_handle::CoarseGraph& G = coarse_graph<T>(h);
+        if (G.exec && G.dense_valid == h->dense.valid && f == w.f) {
+            HIP_TRY(h, hipGraphLaunch(G.exec, h->stream));
+            h->alg_bytes += G.bytes;
+            *result = static_cast<T*>(G.result);
+            return MG_OK;
+        }
+    }
     T* cur = w.xa;
     T* nxt = w.xb;
     if (l == last) {
@@ -378,6 +457,57 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     }
     *result = cur;
     return MG_OK;
+}
+
+// Capture the V-cycle of levels 1..L-1 in precision T as a graph (on the
+// handle's private stream; nothing in it is a memset or an event), for the
+// current options, work buffers and coarsest-level route. Graphs are an
+// optimisation: a capture that fails leaves the cycle to direct launches.
+template <typename T>
+mg_status capture_coarse(mg_handle* h) {
+    mg_handle::CoarseGraph& G = coarse_graph<T>(h);
+    if (G.exec) {
+        (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+    }
+    const bool have = std::is_same<T, float>::value ? h->have32 : h->have64;
+    if (h->lv.size() < 2 || !have || !h->cap_stream || !h->opt.graphs) return MG_OK;
+    hipStream_t user = h->stream;
+    const int profile = h->opt.profile;
+    const double bytes0 = h->alg_bytes;
+    h->stream = h->cap_stream;
+    h->opt.profile = 0;
+    h->no_events = true;
+    h->capturing = true;
+    T* res = nullptr;
+    hipGraph_t graph = nullptr;
+    mg_status s = MG_OK;
+    if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        s = vcycle<T>(h, 1, work<T>(h->lv[1]).f, &res);
+        if (hipStreamEndCapture(h->cap_stream, &graph) != hipSuccess) graph = nullptr;
+    }
+    (void)hipGetLastError();
+    h->stream = user;
+    h->opt.profile = profile;
+    h->no_events = false;
+    h->capturing = false;
+    G.bytes = h->alg_bytes - bytes0;
+    h->alg_bytes = bytes0;
+    if (s == MG_OK && graph &&
+        hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        G.result = res;
+        G.dense_valid = h->dense.valid;
+    } else {
+        G.exec = nullptr;
+        (void)hipGetLastError();
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    return MG_OK;
+}
+
+mg_status capture_graphs(mg_handle* h) {
+    MG_TRY(capture_coarse<float>(h));
+    return capture_coarse<double>(h);
 }
 
 // Transposed smoother chain starting from xbar (no pending column solve):
@@ -500,16 +630,20 @@ mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uou
         double(d.n) * (3 * sizeof(U) + sizeof(T) + (e ? sizeof(T) + sizeof(U) : 0));
     int nb = 0;
     {
-        Launch g(h, MG_K_RESIDUAL64, 0, bytes);
-        nb = mgk::residual_update<U, T, T>(view<U>(d), b, uin, e, uout, r, h->partials,
-                                           with_bnorm ? h->partials + h->max_partials : nullptr,
-                                           h->stream);
-    }
-    MG_TRY(check_launch(h, "residual_update"));
-    {
-        Launch g(h, MG_K_OTHER, 0, double(nb) * 8 * (with_bnorm ? 2 : 1));
-        mgk::sum_partials(h->partials, nb, h->scalar, h->stream, with_bnorm ? 2 : 1,
-                          h->max_partials);
+        Phase ph(h, 1);
+        {
+            Launch g(h, MG_K_RESIDUAL64, 0, bytes);
+            nb = mgk::residual_update<U, T, T>(view<U>(d), b, uin, e, uout, r, h->partials,
+                                               with_bnorm ? h->partials + h->max_partials
+                                                          : nullptr,
+                                               h->stream);
+        }
+        MG_TRY(check_launch(h, "residual_update"));
+        {
+            Launch g(h, MG_K_OTHER, 0, double(nb) * 8 * (with_bnorm ? 2 : 1));
+            mgk::sum_partials(h->partials, nb, h->scalar, h->stream, with_bnorm ? 2 : 1,
+                              h->max_partials);
+        }
     }
     return post_scalar(h);
 }
@@ -530,8 +664,12 @@ mg_status finish_step(mg_handle* h, double* rnorm, double* bnorm = nullptr) {
 // or transposed V-cycle.
 template <typename T, typename U>
 mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* st,
-                bool transposed) {
-    MG_TRY(ensure_work<T>(h));
+                bool transposed, bool* stalled = nullptr) {
+    if (!(std::is_same<T, float>::value ? h->have32 : h->have64)) {
+        // first use of this precision (the FP64 fallback of a mixed solve)
+        MG_TRY(ensure_work<T>(h));
+        MG_TRY(capture_coarse<T>(h));
+    }
     DevLevel& d = h->lv[0];
     Work<T>& w = work<T>(d);
     auto t0 = std::chrono::steady_clock::now();
@@ -565,6 +703,7 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r, true)));
     // enqueue one V-cycle on r; its correction e is what the next step adds
     auto cycle = [&](const T** e) -> mg_status {
+        Phase ph(h, 0);
         if (!transposed) {
             T* x = nullptr;
             MG_TRY(vcycle<T>(h, 0, w.f, &x));
@@ -580,8 +719,17 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     const T* e_ahead = nullptr;   // a V-cycle already enqueued on the current r
     if (h->opt.max_iters > 0) MG_TRY(cycle(&e_ahead));
     MG_TRY(finish_step(h, &rn, &bnorm));
-    std::vector<double> hist{rn};
-    int it = 0;
+    // residual norms, kept in place (no allocation inside a solve)
+    struct Hist {
+        double v[MG_HIST];
+        size_t n = 0;
+        void push_back(double x) { v[n < MG_HIST ? n++ : MG_HIST - 1] = x; }
+        size_t size() const { return n; }
+        double back() const { return v[n - 1]; }
+        double operator[](size_t i) const { return v[i]; }
+    } hist;
+    hist.push_back(rn);
+    int it = 0, slow = 0;
     mg_status status = MG_OK;
     if (!std::isfinite(rn) || !std::isfinite(bnorm)) status = MG_ERR_BREAKDOWN;
     while (status == MG_OK) {
@@ -616,6 +764,14 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
         ++it;
         hist.push_back(rn);
         if (!std::isfinite(rn)) status = MG_ERR_BREAKDOWN;
+        // stagnation guard: the caller continues with FP64 cycles
+        if (stalled && h->opt.stall_iters > 0 && status == MG_OK) {
+            slow = rn > h->opt.stall_factor * hist[hist.size() - 2] ? slow + 1 : 0;
+            if (slow >= h->opt.stall_iters && rn > tol * bnorm) {
+                *stalled = true;
+                break;
+            }
+        }
     }
     if constexpr (std::is_same<U, double>::value) {
         if (ucur != u) {
@@ -677,13 +833,17 @@ mg_status rebuild_dense(mg_handle* h) {
 // Device-side coefficients: masses per level, pivots, FP32 copies.
 mg_status set_coeffs(mg_handle* h, const double* alpha) {
     DevLevel& f = h->lv[0];
-    int nb = mgk::fine_mass(view<double>(f), f.V64, alpha, f.M64, h->partials, h->stream);
+    // count the bad values before anything is written: a rejected alpha
+    // leaves the handle's operator as it was
+    int nb = mgk::fine_mass(view<double>(f), f.V64, alpha, nullptr, h->partials, h->stream);
     mgk::sum_partials(h->partials, nb, h->scalar, h->stream);
-    MG_TRY(check_launch(h, "fine_mass"));
+    MG_TRY(check_launch(h, "alpha check"));
     double bad = 0;
     MG_TRY(sync_scalar(h, &bad));
     if (bad != 0)
         return fail(h, MG_ERR_ARG, "alpha has %.0f values that are not finite and > 0", bad);
+    mgk::fine_mass(view<double>(f), f.V64, alpha, f.M64, h->partials, h->stream);
+    MG_TRY(check_launch(h, "fine_mass"));
     for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
         DevLevel &d = h->lv[l], &c = h->lv[l + 1];
         mgk::restrict_residual<double>(view<double>(d), xview<double>(d, c), d.M64, nullptr,
@@ -719,6 +879,8 @@ mg_status build(mg_handle* h, const double* alpha) {
         MG_TRY(upload(h, &d.Tlam32, s.Tlam));
         MG_TRY(upload(h, &d.Tth32, s.Tth));
         MG_TRY(upload(h, &d.Tr32, s.Tr));
+        MG_TRY(upload(h, &d.sc64, step_table<double>(s)));
+        MG_TRY(upload(h, &d.sc32, step_table<float>(s)));
         MG_TRY(dalloc(h, &d.M64, d.n));
         MG_TRY(dalloc(h, &d.invp64, d.n));
         MG_TRY(dalloc(h, &d.M32, d.n));
@@ -773,6 +935,11 @@ mg_status build(mg_handle* h, const double* alpha) {
 
 void release(mg_handle* h) {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (mg_handle::CoarseGraph* G : {&h->g32, &h->g64})
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    h->g32.exec = h->g64.exec = nullptr;
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    h->cap_stream = nullptr;
     for (void* p : h->allocs) (void)hipFree(p);
     h->allocs.clear();
     if (h->host_scalar) (void)hipHostFree(h->host_scalar);
@@ -856,6 +1023,70 @@ mg_status one_vcycle(mg_handle* h, const double* f, double* x, bool transposed) 
     return check_launch(h, "vcycle");
 }
 
+// The work buffers a solve in the handle's precision uses, allocated ahead
+// of the first solve (mg_setup, mg_set_options), so that a solve itself need
+// not allocate.
+mg_status ensure_buffers(mg_handle* h) {
+    if (h->opt.precision == MG_PREC_FP64) return ensure_work<double>(h);
+    MG_TRY(ensure_work<float>(h));
+    if (h->opt.precision == MG_PREC_FP32 && !h->b32) {
+        const long long n = h->lv[0].n;
+        MG_TRY(dalloc(h, &h->b32, n));
+        MG_TRY(dalloc(h, &h->u32a, n));
+        MG_TRY(dalloc(h, &h->u32b, n));
+    }
+    return MG_OK;
+}
+
+// Forward or adjoint solve in the handle's precision; a mixed solve that
+// stalls continues in FP64 (when fallback is allowed).
+mg_status solve_in_precision(mg_handle* h, const double* rhs, double* u, double tol,
+                             mg_stats* st, bool transposed, bool fallback) {
+    if (h->opt.precision == MG_PREC_FP64)
+        return outer<double, double>(h, rhs, u, tol, st, transposed);
+    if (h->opt.precision == MG_PREC_FP32)
+        return outer<float, float>(h, rhs, u, tol, st, transposed);
+    mg_stats s1{};
+    bool stalled = false;
+    mg_status s = outer<float, double>(h, rhs, u, tol, &s1, transposed,
+                                       fallback ? &stalled : nullptr);
+    if (s == MG_OK && stalled) {
+        // the FP32 cycle stopped contracting: continue from the current
+        // iterate (in u) with FP64 cycles for the remaining iterations
+        mg_stats s2{};
+        const int cap = h->opt.max_iters;
+        h->opt.max_iters = cap - s1.iters;
+        s = outer<double, double>(h, rhs, u, tol, &s2, transposed);
+        h->opt.max_iters = cap;
+        for (int m = 1; m <= s2.iters && s1.iters + m < MG_HIST; ++m)
+            s1.res_hist[s1.iters + m] = s2.res_hist[m];
+        s1.iters += s2.iters;
+        s1.relres = s2.relres;
+        s1.ms_total += s2.ms_total;
+        s1.ms_vcycle += s2.ms_vcycle;
+        s1.ms_residual += s2.ms_residual;
+        s1.alg_bytes += s2.alg_bytes;
+        for (int c = 0; c < MG_NK; ++c) {
+            s1.kern_ms[c] += s2.kern_ms[c];
+            s1.kern_launches[c] += s2.kern_launches[c];
+            s1.kern_bytes[c] += s2.kern_bytes[c];
+            s1.kern_fine_ms[c] += s2.kern_fine_ms[c];
+            s1.kern_fine_launches[c] += s2.kern_fine_launches[c];
+            s1.kern_fine_bytes[c] += s2.kern_fine_bytes[c];
+        }
+        s1.fell_back_fp64 = 1;
+    }
+    if (st) *st = s1;
+    return s;
+}
+
+mg_status check_solve_args(mg_handle* h, const double* rhs, const double* u, double tol) {
+    if (!rhs || !u) return fail(h, MG_ERR_ARG, "NULL field pointer");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(h, MG_ERR_ARG, "tol must be > 0");
+    if (rhs == u) return fail(h, MG_ERR_ARG, "rhs and solution must not alias");
+    return MG_OK;
+}
+
 }  // namespace
 
 // --- C ABI ---------------------------------------------------------------------
@@ -877,6 +1108,9 @@ void mg_options_default(mg_options* o) {
     o->smooth_lo = 1.0 / 3.0;
     o->smooth_hi = 2.0;
     o->staged_columns = 65536;
+    o->stall_factor = 0.9;
+    o->stall_iters = 3;
+    o->graphs = 1;
 }
 
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,
@@ -891,7 +1125,15 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_option
     h->grid = *grid;
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
-    mg_status s = build(h, coeffs->alpha);
+    mg_status s = hipGetDevice(&h->device) == hipSuccess ? MG_OK : MG_ERR_HIP;
+    if (s == MG_OK) s = build(h, coeffs->alpha);
+    if (s == MG_OK) s = ensure_buffers(h);
+    if (s == MG_OK &&
+        hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        h->cap_stream = nullptr;   // no graphs: direct launches
+    }
+    if (s == MG_OK) s = capture_graphs(h);
     if (s != MG_OK) {
         std::fprintf(stderr, "mg_setup: %s\n", h->err.c_str());
         release(h);
@@ -905,7 +1147,13 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_option
 mg_status mg_update_coeffs(mg_handle* h, const mg_coeffs* coeffs) {
     if (!h) return MG_ERR_ARG;
     if (!coeffs || !coeffs->alpha) return fail(h, MG_ERR_ARG, "NULL coefficients");
-    return set_coeffs(h, coeffs->alpha);
+    MG_TRY(set_coeffs(h, coeffs->alpha));
+    // the graphs read the coefficients from the same buffers; only a change
+    // of the coarsest route needs new ones
+    if ((h->g32.exec && h->g32.dense_valid != h->dense.valid) ||
+        (h->g64.exec && h->g64.dense_valid != h->dense.valid))
+        return capture_graphs(h);
+    return MG_OK;
 }
 
 mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
@@ -918,24 +1166,19 @@ mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
     const bool recoarse = opts->coarse_sweeps != h->dense.sweeps || opts->omega != h->dense.omega;
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
+    MG_TRY(ensure_buffers(h));
     if (recoarse && h->dense.enabled) {
         MG_TRY(rebuild_dense(h));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
     }
-    return MG_OK;
+    return capture_graphs(h);
 }
 
 static mg_status solve_common(mg_handle* h, const double* rhs, double* u, double tol,
                               mg_stats* st, bool transposed) {
     if (!h) return MG_ERR_ARG;
-    if (!rhs || !u) return fail(h, MG_ERR_ARG, "NULL field pointer");
-    if (!(tol > 0) || !std::isfinite(tol)) return fail(h, MG_ERR_ARG, "tol must be > 0");
-    if (rhs == u) return fail(h, MG_ERR_ARG, "rhs and solution must not alias");
-    if (h->opt.precision == MG_PREC_FP64)
-        return outer<double, double>(h, rhs, u, tol, st, transposed);
-    if (h->opt.precision == MG_PREC_FP32)
-        return outer<float, float>(h, rhs, u, tol, st, transposed);
-    return outer<float, double>(h, rhs, u, tol, st, transposed);
+    MG_TRY(check_solve_args(h, rhs, u, tol));
+    return solve_in_precision(h, rhs, u, tol, st, transposed, true);
 }
 
 mg_status mg_solve(mg_handle* h, const double* rhs, double* u, double tol, mg_stats* st) {

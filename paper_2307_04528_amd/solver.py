@@ -23,6 +23,9 @@ class SolveStats:
     levels: int
     alg_bytes: float
     kernels: dict
+    ms_vcycle: float = 0.0
+    ms_residual: float = 0.0
+    fell_back_fp64: bool = False
 
     @staticmethod
     def from_c(st: L.mg_stats) -> "SolveStats":
@@ -35,7 +38,8 @@ class SolveStats:
         return SolveStats(int(st.iters), float(st.relres),
                           [float(st.res_hist[m]) for m in range(st.iters + 1)],
                           float(st.ms_total), int(st.levels_used), float(st.alg_bytes),
-                          kernels)
+                          kernels, float(st.ms_vcycle), float(st.ms_residual),
+                          bool(st.fell_back_fp64))
 
 
 def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
@@ -45,11 +49,14 @@ def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
 
 def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, omega=0.8,
              semi_threshold=2.0, precision="mixed", profile=False, stream=None,
-             smooth_interval=(1.0 / 3.0, 2.0), staged_columns=65536) -> L.mg_options:
+             smooth_interval=(1.0 / 3.0, 2.0), staged_columns=65536, stall_factor=0.9,
+             stall_iters=3, graphs=True) -> L.mg_options:
     """smooth_interval: (lo, hi), per-sweep omegas from the Chebyshev nodes of
     [lo, hi] (the default, see mg.h), or None: every smoothing sweep uses
     omega. staged_columns: levels with fewer columns sweep with the staged
-    kernel (0: never)."""
+    kernel (0: never). stall_factor, stall_iters: the mixed solve's switch
+    to FP64 cycles when it stops contracting (see mg.h). graphs: replay the
+    V-cycle below the finest level as a captured HIP graph."""
     o = L.mg_options()
     L.lib().mg_options_default(C.byref(o))
     o.levels = int(levels)
@@ -65,6 +72,8 @@ def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, ome
     else:
         o.smooth_lo, o.smooth_hi = float(smooth_interval[0]), float(smooth_interval[1])
     o.staged_columns = int(staged_columns)
+    o.stall_factor, o.stall_iters = float(stall_factor), int(stall_iters)
+    o.graphs = int(graphs)
     return o
 
 
@@ -128,7 +137,7 @@ class Solver:
         L.check(L.lib().mg_setup(C.byref(self._grid), C.byref(co), C.byref(o), C.byref(h)),
                 what="mg_setup")
         self._h = h
-        self.alpha = alpha
+        self._set_alpha(alpha)
 
     @classmethod
     def from_shell(cls, shell, alpha: torch.Tensor, **opts):
@@ -173,17 +182,33 @@ class Solver:
             pass
 
     # -- API -----------------------------------------------------------------
+    def option(self, name: str):
+        """The value of one mg_options field in effect for this solver."""
+        return getattr(_options(stream=self._stream, **self._opts), name)
+
     def set_options(self, **opts):
         self._opts.update(opts)
         o = _options(stream=self._stream, **self._opts)
         L.check(L.lib().mg_set_options(self._h, C.byref(o)), self._h, "mg_set_options")
+
+    def _set_alpha(self, alpha: torch.Tensor):
+        # the tensor whose values the handle holds, and its memory and version
+        # counter at upload: an in-place change bumps the version (the
+        # reference kept here also keeps the memory from being reused)
+        self.alpha = alpha
+        self._alpha_key = (alpha.data_ptr(), alpha._version)
+
+    def alpha_is_current(self, alpha: torch.Tensor) -> bool:
+        """True if alpha is the tensor last uploaded, unchanged since."""
+        return (alpha.data_ptr(), alpha._version) == self._alpha_key and \
+            alpha.shape == self.alpha.shape
 
     def update_alpha(self, alpha: torch.Tensor):
         self._check(alpha, "alpha")
         self._sync_options()
         co = L.mg_coeffs(alpha.data_ptr())
         L.check(L.lib().mg_update_coeffs(self._h, C.byref(co)), self._h, "mg_update_coeffs")
-        self.alpha = alpha
+        self._set_alpha(alpha)
 
     def solve(self, rhs: torch.Tensor, tol: float = 1e-8, u0: torch.Tensor | None = None,
               out: torch.Tensor | None = None):

@@ -113,3 +113,31 @@ def test_mixed_solve_residual_checked_on_host(sh):
     log(f"  oracle residual of the returned u: {relres:.3e}")
     assert relres <= 1e-8
     assert relres == pytest.approx(st.relres, rel=1e-3)
+
+
+@functools.lru_cache(maxsize=1)
+def bench_oracle_solution():
+    log("[oracle] solve of shell1024x768x70 to relres 1e-12 (about a minute and a half)")
+    u, st = oracle.solve(bench_levels(), shellgen.rhs(BENCH), opts_of(BENCH), tol=1e-12)
+    log(f"  oracle: {st['iters']} iterations, relres {st['relres']:.2e}")
+    return u
+
+
+def test_mixed_solve_forward_error_below_1e8():
+    """The answer of the method is u = H^{-1} b (Section 2). On the
+    benchmark workload, the mixed solve at relative residual 1e-11 is
+    within 1e-8 (relative, 2-norm) of the oracle's own solution, solved to
+    relres 1e-12 with its FP64 V-cycles; at the timed stop, 1e-8, the
+    forward error is larger (the condition number is large), which bench.py
+    reports beside the time."""
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision="mixed", nu_pre=BENCH.nu_pre,
+                   nu_post=BENCH.nu_post)
+    b = t(shellgen.rhs(BENCH))
+    u, st = S.solve(b, tol=1e-11)
+    u = n(u)
+    S.close()
+    uo = bench_oracle_solution()
+    err = rel2(u, uo)
+    log(f"mixed solve to 1e-11: {st.iters} iterations, forward error {err:.2e}")
+    assert st.relres <= 1e-11
+    assert err < 1e-8

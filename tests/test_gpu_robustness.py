@@ -1,0 +1,153 @@
+"""Error paths and guards of the C ABI, on the GPU:
+
+  * alpha that is not finite and > 0 is rejected by mg_setup and by
+    mg_update_coeffs with MG_ERR_ARG, and a rejected update leaves the
+    handle's operator as it was (the next solve is bit-identical);
+  * a non-finite right-hand side ends the solve with MG_ERR_BREAKDOWN;
+  * the stagnation guard of the mixed solve: forced from the host (a
+    stall factor no iteration can beat), the solve continues with FP64
+    cycles from its iterate, reports fell_back_fp64 and still meets the
+    tolerance and the oracle's solution;
+  * the per-phase device times of a solve are filled in;
+  * the autograd wrapper uploads alpha again after an in-place change, and
+    not when alpha is unchanged.
+"""
+import numpy as np
+import pytest
+import torch
+
+import shellgen
+from gpu_util import log, t, n, solver_for, rel2, oracle_solution
+
+from paper_2307_04528_amd import _lib as L
+from paper_2307_04528_amd.autograd import mg_solve
+
+pytestmark = pytest.mark.gpu
+
+SMALL = shellgen.workload("shell64x32x16")
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, np.nan, np.inf])
+def test_setup_rejects_bad_alpha(bad):
+    a = shellgen.alpha(SMALL)
+    a[3, 5, 7] = bad
+    with pytest.raises(L.MGError) as e:
+        solver_for(SMALL, a)
+    assert e.value.status == L.MG_ERR_ARG
+
+
+@pytest.mark.parametrize("bad", [0.0, np.nan])
+def test_rejected_update_leaves_handle_unchanged(bad):
+    a = shellgen.alpha(SMALL)
+    b = t(shellgen.rhs(SMALL))
+    S = solver_for(SMALL, a, nu_pre=1, nu_post=1)
+    u1, st1 = S.solve(b, tol=1e-10)
+    a2 = 1.5 * a
+    a2[0, 0, 0] = bad
+    with pytest.raises(L.MGError) as e:
+        S.update_alpha(t(a2))
+    assert e.value.status == L.MG_ERR_ARG
+    u2, st2 = S.solve(b, tol=1e-10)
+    log(f"after rejected update: iters {st1.iters} -> {st2.iters}")
+    assert st2.iters == st1.iters
+    assert torch.equal(u1, u2)
+
+
+def test_nan_rhs_is_breakdown():
+    a = shellgen.alpha(SMALL)
+    S = solver_for(SMALL, a, nu_pre=1, nu_post=1)
+    bh = shellgen.rhs(SMALL)
+    bh[2, 3, 4] = np.nan
+    with pytest.raises(L.MGError) as e:
+        S.solve(t(bh), tol=1e-8)
+    assert e.value.status == L.MG_ERR_BREAKDOWN
+
+
+def test_stall_guard_continues_in_fp64():
+    sh = SMALL
+    a = shellgen.alpha(sh)
+    b = t(shellgen.rhs(sh))
+    uo, _ = oracle_solution(sh)
+    # every iteration counts as stalled: the guard fires after two
+    S = solver_for(sh, a, nu_pre=1, nu_post=1, stall_factor=1e-30, stall_iters=2)
+    u, st = S.solve(b, tol=1e-10)
+    err = rel2(n(u), uo)
+    log(f"guarded: iters {st.iters} fell_back {st.fell_back_fp64} relres {st.relres:.2e} "
+        f"err {err:.2e}")
+    assert st.fell_back_fp64
+    assert st.relres <= 1e-10
+    assert len(st.res_hist) == st.iters + 1
+    assert all(np.isfinite(st.res_hist))
+    assert err < 1e-8
+    S.set_options(stall_iters=0)
+    u0, st0 = S.solve(b, tol=1e-10)
+    assert not st0.fell_back_fp64
+    assert rel2(n(u0), uo) < 1e-8
+    S.set_options(stall_factor=0.9, stall_iters=3)
+    u1, st1 = S.solve(b, tol=1e-10)
+    assert not st1.fell_back_fp64
+
+
+def test_phase_times():
+    sh = shellgen.workload("shell384x192x70")
+    S = solver_for(sh, shellgen.alpha(sh))
+    _, st = S.solve(t(shellgen.rhs(sh)), tol=1e-8)
+    log(f"phases: vcycle {st.ms_vcycle:.2f} ms, residual {st.ms_residual:.2f} ms, "
+        f"total {st.ms_total:.2f} ms over {st.iters} iterations")
+    assert st.ms_vcycle > 0 and st.ms_residual > 0
+    assert st.ms_vcycle + st.ms_residual <= 1.05 * st.ms_total
+    assert st.ms_residual < st.ms_vcycle
+
+
+def test_autograd_uploads_alpha_after_inplace_change():
+    sh = SMALL
+    a = t(shellgen.alpha(sh))
+    b = t(shellgen.rhs(sh))
+    from paper_2307_04528_amd import Solver
+    S = Solver.from_shell(sh, a, nu_pre=1, nu_post=1)   # holds this very tensor
+    uploads = []
+    orig = S.update_alpha
+
+    def counting(x):
+        uploads.append(1)
+        return orig(x)
+
+    S.update_alpha = counting
+    mg_solve(b, a, S, 1e-12)
+    assert not uploads, "an unchanged alpha was uploaded again"
+    a.mul_(1.5)
+    u2 = mg_solve(b, a, S, 1e-12)
+    assert len(uploads) == 1
+    ref = solver_for(sh, n(a), nu_pre=1, nu_post=1)
+    ur, _ = ref.solve(b, tol=1e-12)
+    d = rel2(n(u2), n(ur))
+    log(f"after in-place alpha change: {d:.2e} from a fresh handle")
+    assert d < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replays_match_direct_launches(prec):
+    """The V-cycle below the finest level, replayed from its captured graph,
+    gives bit-identical solves to direct launches, on every one of several
+    replays with eager work and synchronisations between them, and after an
+    option change (a new capture)."""
+    sh = shellgen.workload("shell384x192x70")
+    a = shellgen.alpha(sh)
+    b = t(shellgen.rhs(sh))
+    Sg = solver_for(sh, a, precision=prec, graphs=True)
+    Sd = solver_for(sh, a, precision=prec, graphs=False)
+    ud, std_ = Sd.solve(b, tol=1e-9)
+    for rep in range(4):
+        ug, stg = Sg.solve(b, tol=1e-9)
+        torch.cuda.synchronize()
+        assert stg.iters == std_.iters and stg.relres == std_.relres, rep
+        assert torch.equal(ug, ud), rep
+        junk = torch.randn_like(b).mul_(2.0).sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+    for S in (Sg, Sd):
+        S.set_options(omega=0.7, coarse_sweeps=30)
+    ud2, _ = Sd.solve(b, tol=1e-9)
+    ug2, _ = Sg.solve(b, tol=1e-9)
+    assert torch.equal(ug2, ud2)
+    log(f"graph replays ({prec}): bit-identical over {rep + 1} solves and a re-capture")

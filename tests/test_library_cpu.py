@@ -77,7 +77,9 @@ def test_host_tables_match_oracle(sh):
                                  dict(omega=2.5), dict(nu_pre=0), dict(max_iters=500),
                                  dict(semi_threshold=0.0), dict(staged_columns=-1),
                                  dict(profile=4),
-                                 dict(smooth_interval=(2.0, 1.0))])
+                                 dict(smooth_interval=(2.0, 1.0)),
+                                 dict(stall_factor=0.0), dict(stall_iters=-1),
+                                 dict(graphs=2), dict(nlon=4096, nlat=2048, nlev=64)])
 def test_host_argument_validation(bad):
     ensure_library()
     from paper_2307_04528_amd import mg_plan

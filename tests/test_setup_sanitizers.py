@@ -1,0 +1,31 @@
+"""The host-side planner (geometry tables, coarsening and transfer maps; the
+code behind mg_setup, mg_plan and mg_plan_tables) built with g++ under
+AddressSanitizer and UndefinedBehaviorSanitizer and run over a few thousand
+grids and options, checking the invariants the device kernels rely on."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2307_04528_amd", "csrc")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_setup_under_asan_ubsan(tmp_path):
+    exe = str(tmp_path / "setup_sanitized")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(CSRC, "setup.cpp"),
+           os.path.join(ROOT, "tests", "setup_sanitize_driver.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    print(r.stdout)
+    assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
+    assert "0 failures" in r.stdout
