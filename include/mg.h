@@ -238,6 +238,21 @@ mg_status mg_solve(mg_handle* h, const double* rhs, double* u, double tol,
 mg_status mg_solve_adjoint(mg_handle* h, const double* w, double* lambda,
                            double tol, mg_stats* stats);
 
+/* mg_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, same arguments and results, but it allocates nothing.
+ * It records no HIP events (stats->kern_* and ms_vcycle/ms_residual stay
+ * 0; profiling options are ignored for the call), its norm partials go to
+ * a device array of the library's own (one per GPU, kept until the process
+ * ends; grids whose finest level has more than 8.4M columns are rejected
+ * with MG_ERR_ARG), and it needs the work buffers of the handle's
+ * precision, which mg_setup and mg_set_options allocate (MG_ERR_ARG if they
+ * are missing). The stagnation guard switches to FP64 only if the FP64
+ * buffers exist (after an FP64 solve on the handle). Calls that overlap on
+ * one GPU race on that array: serialise them. */
+mg_status mg_solve_noalloc(mg_handle* h, const double* rhs, double* u, double tol,
+                           mg_stats* stats);
+
 /* grad = -lambda * V * u elementwise (dL/dalpha for L = <w, u>). */
 mg_status mg_grad_alpha(mg_handle* h, const double* lambda, const double* u,
                         double* grad);

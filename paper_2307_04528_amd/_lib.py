@@ -69,6 +69,7 @@ _SIGS = {
     "mg_set_options": (_I, [_H, C.POINTER(mg_options)]),
     "mg_solve": (_I, [_H, _P, _P, _D, C.POINTER(mg_stats)]),
     "mg_solve_adjoint": (_I, [_H, _P, _P, _D, C.POINTER(mg_stats)]),
+    "mg_solve_noalloc": (_I, [_H, _P, _P, _D, C.POINTER(mg_stats)]),
     "mg_grad_alpha": (_I, [_H, _P, _P, _P]),
     "mg_apply": (_I, [_H, _P, _P]),
     "mg_cell_volumes": (_I, [_H, _P]),

@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -99,7 +100,7 @@ struct mg_handle {
     int max_partials = 0;
     size_t max_lds = 64 * 1024;    // LDS bytes a block may use (device limit)
     int device = 0;                // the GPU the handle lives on
-    bool no_events = false;        // record no HIP events (during graph capture)
+    bool no_events = false;        // record no HIP events (mg_solve_noalloc)
     bool have32 = false, have64 = false;
     DenseCoarse dense;
     // The V-cycle below the finest level (levels 1..L-1), per precision,
@@ -112,6 +113,7 @@ struct mg_handle {
     } g32, g64;
     hipStream_t cap_stream = nullptr; // private stream the graphs are captured on
     bool capturing = false;
+    bool no_graphs = false;           // replay none (mg_solve_noalloc)
     std::string err;
     std::vector<ProfRec> recs;
     std::vector<ProfRec> phases;   // cls 0: a V-cycle, 1: a refinement step
@@ -397,7 +399,7 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     DevLevel& d = h->lv[l];
     Work<T>& w = work<T>(d);
     const int last = int(h->lv.size()) - 1;
-    if (l == 1 && !h->capturing && h->opt.profile != 2) {
+    if (l == 1 && !h->capturing && !h->no_graphs && h->opt.profile != 2) {
         mg_handle::CoarseGraph& G = coarse_graph<T>(h);
         if (G.exec && G.dense_valid == h->dense.valid && f == w.f) {
             HIP_TRY(h, hipGraphLaunch(G.exec, h->stream));
@@ -1023,6 +1025,29 @@ mg_status one_vcycle(mg_handle* h, const double* f, double* x, bool transposed) 
     return check_launch(h, "vcycle");
 }
 
+// Scratch of mg_solve_noalloc: the per-block norm partials of the
+// refinement steps and the two reduced norms, in a device array of the
+// library's own. Each GPU holds one copy (until the process ends); its
+// address there is looked up once, at the first mg_setup on that GPU, with
+// that GPU current. Host code uses that address, never the array's name.
+constexpr size_t kScratchDoubles = 65536 + 256;
+__device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+double* g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mutex;
+
+mg_status init_scratch(mg_handle* h) {
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (h->device < 0 || h->device >= kMaxDevices)
+        return fail(h, MG_ERR_ARG, "device %d out of range", h->device);
+    if (!g_scratch[h->device]) {
+        void* p = nullptr;
+        HIP_TRY(h, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch[h->device] = static_cast<double*>(p);
+    }
+    return MG_OK;
+}
+
 // The work buffers a solve in the handle's precision uses, allocated ahead
 // of the first solve (mg_setup, mg_set_options), so that a solve itself need
 // not allocate.
@@ -1126,6 +1151,7 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_option
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
     mg_status s = hipGetDevice(&h->device) == hipSuccess ? MG_OK : MG_ERR_HIP;
+    if (s == MG_OK) s = init_scratch(h);
     if (s == MG_OK) s = build(h, coeffs->alpha);
     if (s == MG_OK) s = ensure_buffers(h);
     if (s == MG_OK &&
@@ -1188,6 +1214,40 @@ mg_status mg_solve(mg_handle* h, const double* rhs, double* u, double tol, mg_st
 mg_status mg_solve_adjoint(mg_handle* h, const double* w, double* lambda, double tol,
                            mg_stats* st) {
     return solve_common(h, w, lambda, tol, st, true);
+}
+
+mg_status mg_solve_noalloc(mg_handle* h, const double* rhs, double* u, double tol,
+                           mg_stats* st) {
+    if (!h) return MG_ERR_ARG;
+    MG_TRY(check_solve_args(h, rhs, u, tol));
+    double* sp = (h->device >= 0 && h->device < kMaxDevices) ? g_scratch[h->device] : nullptr;
+    if (!sp) return fail(h, MG_ERR_ARG, "no scratch address for device %d", h->device);
+    const size_t need = 2 * size_t(h->max_partials) + 2;
+    if (need > kScratchDoubles)
+        return fail(h, MG_ERR_ARG,
+                    "grid too large for mg_solve_noalloc: %zu scratch values needed, %zu "
+                    "available", need, kScratchDoubles);
+    const bool ready = h->opt.precision == MG_PREC_FP64 ? h->have64
+                       : h->opt.precision == MG_PREC_FP32 ? (h->have32 && h->b32)
+                                                          : h->have32;
+    if (!ready)
+        return fail(h, MG_ERR_ARG, "the work buffers of this precision are not allocated");
+    // run on the scratch, with no events and no profiling; restore after
+    double* partials = h->partials;
+    double* scalar = h->scalar;
+    const int profile = h->opt.profile;
+    h->partials = sp;
+    h->scalar = sp + 2 * size_t(h->max_partials);
+    h->no_events = true;
+    h->no_graphs = true;
+    h->opt.profile = 0;
+    mg_status s = solve_in_precision(h, rhs, u, tol, st, false, h->have64);
+    h->partials = partials;
+    h->scalar = scalar;
+    h->no_events = false;
+    h->no_graphs = false;
+    h->opt.profile = profile;
+    return s;
 }
 
 mg_status mg_grad_alpha(mg_handle* h, const double* lambda, const double* u, double* g) {
