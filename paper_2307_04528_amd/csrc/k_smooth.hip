@@ -180,6 +180,13 @@ struct StencilRaw {
     T f, c, w, e, s, n;
 };
 
+// The loads of one layer of a coarsest-level sweep: the stencil values and
+// the row's horizontal couplings.
+template <typename T>
+struct CoarseRaw {
+    T f, c, w, e, s, n, tl, ts, tn;
+};
+
 // Keep the old iterate of a column in registers between the two passes
 // (FP32), or load it again in the back-substitution (FP64).
 template <typename T>
@@ -433,8 +440,10 @@ __global__ __launch_bounds__(kBlock) void k_coarse_solve(LevelView<T> L, const T
 // UNIT: block b solves for the b-th unit vector instead of f and writes its
 // result to row b of xout (rows of n values): the grid then computes the
 // solve's explicit matrix, transposed, one row per block. The unit
-// right-hand side is formed on the fly, not stored: the smaller LDS
-// footprint lets two blocks share a CU on more levels.
+// right-hand side is formed on the fly, not stored, and the horizontal
+// coupling tables are read from global memory (L1 hits, fetched with the
+// iterate one chunk ahead) instead of LDS: the smaller LDS footprint lets
+// two blocks share a CU on the 4200-cell coarsest levels.
 template <typename T, int NZ, bool UNIT>
 __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* __restrict__ f,
                                                        T* __restrict__ xout, T omega,
@@ -445,17 +454,19 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     T* sx = reinterpret_cast<T*>(smem_raw);
     T* sf = sx + n;                  // right-hand side (not UNIT)
     T* sp = sf + (UNIT ? 0 : n);
-    T* stl = sp + n;                 // [nz][nJ]
-    T* sth = stl + nz * nJ;          // [nz][nJ+1]
-    T* str = sth + nz * (nJ + 1);    // [nz+1][nJ]
+    T* stl = sp + n;                 // [nz][nJ] (not UNIT)
+    T* sth = stl + (UNIT ? 0 : nz * nJ);        // [nz][nJ+1] (not UNIT)
+    T* str = sth + (UNIT ? 0 : nz * (nJ + 1));  // [nz+1][nJ]
     T* xch = str + (nz + 1) * nJ;    // 256 per pair
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         sx[t] = T(0);   // the first sweep starts from zero: same code as the rest
         if constexpr (!UNIT) sf[t] = f[t];
         sp[t] = L.invp[t];
     }
-    for (int t = threadIdx.x; t < nz * nJ; t += blockDim.x) stl[t] = L.Tlam[t];
-    for (int t = threadIdx.x; t < nz * (nJ + 1); t += blockDim.x) sth[t] = L.Tth[t];
+    if constexpr (!UNIT) {
+        for (int t = threadIdx.x; t < nz * nJ; t += blockDim.x) stl[t] = L.Tlam[t];
+        for (int t = threadIdx.x; t < nz * (nJ + 1); t += blockDim.x) sth[t] = L.Tth[t];
+    }
     for (int t = threadIdx.x; t < (nz + 1) * nJ; t += blockDim.x) str[t] = L.Tr[t];
     __syncthreads();
     const PairOf p = pair_of_wave();
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
         asm volatile("" : "+s"(pl), "+s"(nj));
         auto fetch = [&](int, int kk) {
             const T* xl = sx + kk * pl;
-            StencilRaw<T> r;
+            CoarseRaw<T> r;
             if constexpr (UNIT) r.f = (kk * pl + int(b.c) == int(blockIdx.x)) ? T(1) : T(0);
             else r.f = sf[kk * pl + b.c];
             r.c = xl[b.c];
@@ -487,12 +498,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
             r.e = xl[b.e];
             r.s = xl[b.s];
             r.n = xl[b.n];
+            const T* tl = UNIT ? L.Tlam : stl;
+            const T* th = UNIT ? L.Tth : sth;
+            r.tl = tl[kk * nj + b.J];
+            r.ts = th[kk * (nj + 1) + b.J];
+            r.tn = th[kk * (nj + 1) + b.J + 1];
             return r;
         };
-        auto comb = [&](int t, int kk, const StencilRaw<T>& r) -> T {
+        auto comb = [&](int t, int kk, const CoarseRaw<T>& r) -> T {
             xk[t] = r.c;
-            return r.f + stl[kk * nj + b.J] * (r.w + r.e) + sth[kk * (nj + 1) + b.J] * r.s +
-                   sth[kk * (nj + 1) + b.J + 1] * r.n;
+            return r.f + r.tl * (r.w + r.e) + r.ts * r.s + r.tn * r.n;
         };
         auto inv = [&](int kk) -> T { return sp[kk * pl + b.c]; };
         auto cpl = [&](int F) -> T { return str[F * nj + b.J]; };

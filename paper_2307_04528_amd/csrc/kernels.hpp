@@ -82,11 +82,13 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
 
 // LDS bytes of the one-block coarsest solve: f, pivots and iterate per cell,
 // the three coefficient tables, and the exchange slots of two wavefront
-// pairs. unit: the unit-vector solves of coarse_basis, which store no f.
+// pairs. unit: the unit-vector solves of coarse_basis, which store no f and
+// read the two horizontal tables from global memory.
 template <typename T>
 inline size_t coarse_lds_bytes(long long plane, int nJ, int nz, bool unit = false) {
-    return ((unit ? 2 : 3) * size_t(plane) * size_t(nz) + size_t(nz) * nJ +
-            size_t(nz) * (nJ + 1) + size_t(nz + 1) * nJ + 512) * sizeof(T);
+    const size_t horiz = unit ? 0 : size_t(nz) * nJ + size_t(nz) * (nJ + 1);
+    return ((unit ? 2 : 3) * size_t(plane) * size_t(nz) + horiz + size_t(nz + 1) * nJ + 512) *
+           sizeof(T);
 }
 
 // The coarsest-level solve (`sweeps` sweeps from zero) is a linear map
