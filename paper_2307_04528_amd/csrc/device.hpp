@@ -167,10 +167,95 @@ __device__ __forceinline__ void stb(gptr base, uint32_t boff, T v) {
     *(__attribute__((address_space(1))) T*)(base + boff) = v;
 }
 
+// Buffer instructions. A raw buffer resource over `bytes` bytes at p (32-bit
+// data format, no stride); an access gives a per-lane byte offset and a
+// wave-uniform one, so the per-cell arrays of a level, which share one
+// layout, address layer k of any of them with the same scalar offset.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(bytes),
+                                             0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff),
+                                                                          int(soff), 0));
+}
+template <>
+__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff),
+                                                                           int(soff), 0));
+}
+__device__ __forceinline__ void bst(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff),
+                                          int(soff), 0);
+}
+__device__ __forceinline__ void bst(double v, rsrc_t r, uint32_t voff, uint32_t soff) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff),
+                                          0);
+}
+
+// Two adjacent values (a lane's two longitude children) with one load.
+template <typename T>
+using pair_t = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ pair_t<T> bld2(rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ pair_t<float> bld2<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(pair_t<float>,
+                              __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
+}
+template <>
+__device__ __forceinline__ pair_t<double> bld2<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(pair_t<double>,
+                              __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
+}
+
 // Read-only coefficient tables through the constant address space.
 template <typename T>
 __device__ __forceinline__ T tab(const T* p, int idx) {
     return ((const __attribute__((address_space(4))) T*)p)[idx];
+}
+
+// Record i of a step table, through the constant address space (the index
+// is wave-uniform: one scalar load).
+template <typename T>
+__device__ __forceinline__ StepCoef<T> step_rec(const StepCoef<T>* p, size_t i) {
+    const __attribute__((address_space(4))) T* q =
+        (const __attribute__((address_space(4))) T*)(p + i);
+    return {q[0], q[1], q[2], q[3]};
+}
+
+// Lane shifts of a wavefront by one lane (DPP wave_shr / wave_shl): lane l
+// takes src of lane l-1 (from_below) or l+1 (from_above); the lane with no
+// source (0, respectively 63) keeps `edge`.
+__device__ __forceinline__ float from_below(float edge, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, src),
+                                                                 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_above(float edge, float src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, src),
+                                                                 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_below(double edge, double src) {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    const i2 e = __builtin_bit_cast(i2, edge), s = __builtin_bit_cast(i2, src);
+    const i2 r = {__builtin_amdgcn_update_dpp(e.x, s.x, 0x138, 0xf, 0xf, false),
+                  __builtin_amdgcn_update_dpp(e.y, s.y, 0x138, 0xf, 0xf, false)};
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double from_above(double edge, double src) {
+    typedef int i2 __attribute__((ext_vector_type(2)));
+    const i2 e = __builtin_bit_cast(i2, edge), s = __builtin_bit_cast(i2, src);
+    const i2 r = {__builtin_amdgcn_update_dpp(e.x, s.x, 0x130, 0xf, 0xf, false),
+                  __builtin_amdgcn_update_dpp(e.y, s.y, 0x130, 0xf, 0xf, false)};
+    return __builtin_bit_cast(double, r);
 }
 
 // The value of x in lane l (l wave-uniform).

@@ -20,6 +20,26 @@ constexpr int kResidualSync = 4;
 // launch against 4-row tiles without the barrier.
 constexpr int kResidualTallBlocks = 512;
 constexpr int kResidualTallRows = 16;
+// The walking refinement step: a range of layers per wavefront (the whole
+// column of the 70-layer workloads; 35 or 16 layers on shallower levels),
+// the layers whose loads are in flight ahead of the one being computed, and
+// the rows of a block's tile. Measured on the 1024x768x70 shell (mixed
+// solve, per launch): 446 us with whole columns, 458 us with two ranges of
+// 35 layers; 450 us with 4-row tiles against 458 us with 16-row tiles;
+// loads 2 or 4 layers ahead 467 and 468 us; barriers every 8 layers or
+// none 454 and 459 us; longitude neighbours loaded instead of shifted from
+// the neighbour lanes 489 us.
+constexpr int kResidualRange = 70;
+constexpr int kResidualMidRange = 35;
+constexpr int kResidualShortRange = 16;
+constexpr int kResidualAhead = 3;
+constexpr int kResidualWalkRows = 4;
+
+static int residual_walk_range(int nz) {
+    return nz <= kResidualShortRange ? kResidualShortRange
+           : nz <= kResidualMidRange ? kResidualMidRange
+                                     : kResidualRange;
+}
 
 static int residual_tile_rows(int nI, int nJ) {
     return dev::tiled_blocks(nJ, dev::segments_per_row(nI), kResidualTallRows) >=
@@ -104,6 +124,137 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
             // keep the block's wavefronts within a few layers of each other
             if (k % kResidualSync == kResidualSync - 1) __syncthreads();
         }
+    }
+    if (partials_b) block_sum2_to(acc, accb, partials + blockIdx.x, partials_b + blockIdx.x);
+    else block_sum_to(acc, partials + blockIdx.x);
+}
+
+// The same refinement step on levels whose step records cover every layer
+// (nz <= kStepStride), walking ranges of LR layers: block b takes range
+// b / tiles and the tile of R consecutive rows of one 64-column range
+// b % tiles (one wavefront per row), and each wavefront walks its layers
+// upward with the loads of the next P layers in flight, the layers below and
+// above coming from the steps before and after. A row's couplings are its
+// upward step record. FULLI: nI is a multiple of 64, so a lane's longitude
+// neighbours are its neighbour lanes' values, and only lanes 0 and 63 load
+// theirs. Every S layers the block's wavefronts meet at a barrier, so that
+// the latitude neighbours they read are still in L2.
+template <typename TU, typename TE, typename TR, bool HAS_E, int LR, int P, int R, int S,
+          bool FULLI>
+__global__ __launch_bounds__(64 * R) void k_residual_walk(
+    LevelView<TU> L, const TU* __restrict__ bv, const TU* __restrict__ uin,
+    const TE* __restrict__ e, TU* __restrict__ uout, TR* __restrict__ r,
+    double* __restrict__ partials, double* __restrict__ partials_b, int wpr, int tiles) {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int blk = int(logical_block());
+    const int rg = blk / tiles;
+    const Seg g = tiled_segment(blk - rg * tiles, wave, R, L.nI, L.nJ, wpr);
+    const int nz = L.nz, kb = rg * LR;
+    const uint32_t PU = uint32_t(L.plane) * sizeof(TU), PE = uint32_t(L.plane) * sizeof(TE),
+                   PR = uint32_t(L.plane) * sizeof(TR);
+    const rsrc_t ru = make_rsrc(uin, PU * uint32_t(nz)), rb = make_rsrc(bv, PU * uint32_t(nz)),
+                 rm = make_rsrc(L.M, PU * uint32_t(nz)),
+                 re = make_rsrc(HAS_E ? (const void*)e : (const void*)uin, PE * uint32_t(nz)),
+                 rw = make_rsrc(HAS_E ? (const void*)uout : (const void*)uin, PU * uint32_t(nz)),
+                 rr = make_rsrc(r, PR * uint32_t(nz));
+    const bool lane0 = (threadIdx.x & 63u) == 0;
+    const uint32_t gcol = FULLI ? (lane0 ? g.w : g.e) : 0u;
+    const uint32_t uc = g.c * sizeof(TU), us = g.s * sizeof(TU), un = g.n * sizeof(TU),
+                   uw = (FULLI ? gcol : g.w) * sizeof(TU), ue = g.e * sizeof(TU);
+    const uint32_t ec = g.c * sizeof(TE), es = g.s * sizeof(TE), en = g.n * sizeof(TE),
+                   ew = (FULLI ? gcol : g.w) * sizeof(TE), ee = g.e * sizeof(TE);
+    const uint32_t rc = g.c * sizeof(TR);
+    const StepCoef<TU>* qp = L.sc + size_t(g.J) * kStepStride;
+
+    // u + e at a cell of layer offsets (so_u, so_e)
+    auto un_at = [&](uint32_t ou, uint32_t oe, uint32_t so_u, uint32_t so_e) -> TU {
+        TU v = bld<TU>(ru, ou, so_u);
+        if constexpr (HAS_E) v += TU(bld<TE>(re, oe, so_e));
+        return v;
+    };
+    struct Lay {
+        TU uc, us, un, uw, ue, b, m;
+        TE ec, es, en, ew, ee;
+        StepCoef<TU> q;
+    };
+    // the loads of step t (layer kb + t, clamped); only the column itself
+    // for the layer above the range
+    auto fetch = [&](int t, bool column_only) {
+        Lay Q;
+        if constexpr (!HAS_E) Q.ec = Q.es = Q.en = Q.ew = Q.ee = TE(0);
+        const int k = clampk(kb + t, nz);
+        const uint32_t su = uint32_t(k) * PU, se = uint32_t(k) * PE;
+        Q.uc = bld<TU>(ru, uc, su);
+        if constexpr (HAS_E) Q.ec = bld<TE>(re, ec, se);
+        if (!column_only) {
+            Q.us = bld<TU>(ru, us, su);
+            Q.un = bld<TU>(ru, un, su);
+            Q.uw = bld<TU>(ru, uw, su);
+            if constexpr (!FULLI) Q.ue = bld<TU>(ru, ue, su);
+            if constexpr (HAS_E) {
+                Q.es = bld<TE>(re, es, se);
+                Q.en = bld<TE>(re, en, se);
+                Q.ew = bld<TE>(re, ew, se);
+                if constexpr (!FULLI) Q.ee = bld<TE>(re, ee, se);
+            }
+            Q.b = bld<TU>(rb, uc, su);
+            Q.m = bld<TU>(rm, uc, su);
+            Q.q = step_rec(qp, size_t(k));
+        }
+        return Q;
+    };
+    auto sum = [](TU u, TE x) -> TU {
+        if constexpr (HAS_E) return u + TU(x);
+        else return u;
+    };
+
+    // the layer below the range, and its vertical coupling to the first
+    // layer (0 at the bottom)
+    const int kbm = kb > 0 ? kb - 1 : 0;
+    const TU um0 = un_at(uc, ec, uint32_t(kbm) * PU, uint32_t(kbm) * PE);
+    const TU tbm = step_rec(qp, size_t(kbm)).tc;
+    TU um = um0, tb = kb > 0 ? tbm : TU(0);
+    double acc = 0, accb = 0;
+    Lay buf[P + 1];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        buf[t] = fetch(t, t == LR);
+    }
+#pragma unroll
+    for (int t = 0; t < LR; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + P <= LR) buf[(t + P) % (P + 1)] = fetch(t + P, t + P == LR);
+        __builtin_amdgcn_sched_barrier(0);
+        const Lay& c = buf[t % (P + 1)];
+        const Lay& a = buf[(t + 1) % (P + 1)];
+        const TU xc = sum(c.uc, c.ec), xp = sum(a.uc, a.ec);
+        const TU xs = sum(c.us, c.es), xn = sum(c.un, c.en);
+        TU xw, xe;
+        if constexpr (FULLI) {
+            const TU edge = sum(c.uw, c.ew);
+            xw = from_below(edge, xc);
+            xe = from_above(edge, xc);
+        } else {
+            xw = sum(c.uw, c.ew);
+            xe = sum(c.ue, c.ee);
+        }
+        const StepCoef<TU> q = c.q;
+        const TU h = c.m * xc + hdiff(q.tl, q.ts, q.tn, xc, xw, xe, xs, xn) + tb * (xc - um) +
+                     q.tc * (xc - xp);
+        TU rv = c.b - h;
+        // computed here, not sunk (with its loads) into the guarded stores
+        asm volatile("" : "+v"(rv));
+        const int k = kb + t;
+        if (k < nz && g.valid) {
+            if constexpr (HAS_E) bst(xc, rw, uc, uint32_t(k) * PU);
+            bst(TR(rv), rr, rc, uint32_t(k) * PR);
+            acc += double(rv) * double(rv);
+            accb += double(c.b) * double(c.b);
+        }
+        um = xc;
+        tb = q.tc;
+        if (t % S == S - 1) __syncthreads();
     }
     if (partials_b) block_sum2_to(acc, accb, partials + blockIdx.x, partials_b + blockIdx.x);
     else block_sum_to(acc, partials + blockIdx.x);
@@ -246,6 +397,30 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
     const int wpr = segments_per_row(L.nI);
     const int nb = residual_update_blocks(L);
     const bool tall = residual_tile_rows(L.nI, L.nJ) == kResidualTallRows;
+    if (L.nz <= kStepStride) {
+        const int tiles = tiled_blocks(L.nJ, wpr, kResidualWalkRows);
+        const bool full = L.nI % 64 == 0;
+        auto go = [&](auto lrc, auto fullc) {
+            constexpr int LR = decltype(lrc)::value, R = kResidualWalkRows;
+            constexpr bool FULLI = decltype(fullc)::value;
+            constexpr int P = kResidualAhead, S = kResidualSync;
+            if (e)
+                k_residual_walk<TU, TE, TR, true, LR, P, R, S, FULLI>
+                    <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
+            else
+                k_residual_walk<TU, TE, TR, false, LR, P, R, S, FULLI>
+                    <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
+        };
+        auto by_full = [&](auto lrc) {
+            if (full) go(lrc, std::true_type{});
+            else go(lrc, std::false_type{});
+        };
+        const int lr = residual_walk_range(L.nz);
+        if (lr == kResidualShortRange) by_full(std::integral_constant<int, kResidualShortRange>{});
+        else if (lr == kResidualMidRange) by_full(std::integral_constant<int, kResidualMidRange>{});
+        else by_full(std::integral_constant<int, kResidualRange>{});
+        return nb;
+    }
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
 #define MG_RESIDUAL_LAUNCH(HE, R) \
@@ -264,7 +439,10 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
 
 template <typename TU>
 int residual_update_blocks(const LevelView<TU>& L) {
-    return tiled_blocks(L.nJ, segments_per_row(L.nI), residual_tile_rows(L.nI, L.nJ));
+    const int wpr = segments_per_row(L.nI);
+    if (L.nz > kStepStride) return tiled_blocks(L.nJ, wpr, residual_tile_rows(L.nI, L.nJ));
+    const int lr = residual_walk_range(L.nz);
+    return tiled_blocks(L.nJ, wpr, kResidualWalkRows) * ((L.nz + lr - 1) / lr);
 }
 
 void sum_partials(const double* partials, int n, double* out, hipStream_t s, int count,

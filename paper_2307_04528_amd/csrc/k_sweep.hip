@@ -31,36 +31,6 @@ namespace mgk {
 namespace {
 using namespace dev;
 
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-
-// Raw buffer resource over `bytes` bytes at p (32-bit data format, no
-// stride): offsets are byte offsets from p.
-__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(bytes),
-                                             0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff),
-                                                                          int(soff), 0));
-}
-template <>
-__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff),
-                                                                           int(soff), 0));
-}
-__device__ __forceinline__ void bst(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff),
-                                          int(soff), 0);
-}
-__device__ __forceinline__ void bst(double v, rsrc_t r, uint32_t voff, uint32_t soff) {
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff),
-                                          0);
-}
-
 // Per instantiation: D layers per prefetch chunk (5 divides the 35 steps of
 // a 70-layer wavefront; 4 otherwise), W waves per SIMD (the register
 // budget), KX: keep the old iterate of the half-column in LDS between the two
@@ -82,15 +52,7 @@ struct SweepCfg {
 };
 // wavefront pairs per block
 constexpr int kSweepPairs = 2;
-
-// Record i of a step table, through the constant address space (the index
-// is wave-uniform: one scalar load).
-template <typename T>
-__device__ __forceinline__ StepCoef<T> step_rec(const StepCoef<T>* p, size_t i) {
-    const __attribute__((address_space(4))) T* q =
-        (const __attribute__((address_space(4))) T*)(p + i);
-    return {q[0], q[1], q[2], q[3]};
-}
+constexpr bool kSweepShift = true;
 
 // The raw loads of one step: right-hand side, inverse pivot, and the old
 // iterate at the cell and its four horizontal neighbours.
@@ -104,7 +66,7 @@ struct Raw {
 // step records.
 template <typename T>
 struct SegData {
-    uint32_t oc, ow, oe, os, on;
+    uint32_t oc, ow, oe, os, on, og;
     bool valid;
     const StepCoef<T>* cr;
     __device__ __forceinline__ SegData(const LevelView<T>& L, int tile, int pair, bool top,
@@ -113,6 +75,7 @@ struct SegData {
         oc = g.c * sizeof(T);
         ow = g.w * sizeof(T);
         oe = g.e * sizeof(T);
+        og = (threadIdx.x & 63u) == 0 ? ow : oe;
         os = g.s * sizeof(T);
         on = g.n * sizeof(T);
         valid = g.valid;
@@ -132,6 +95,9 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
     constexpr int NS = C::NS;
     constexpr int NC = NS / D;
     constexpr bool KX = HAS_X && C::KX;
+    // every lane has a column and loads the old iterate at it: the longitude
+    // neighbours are the neighbour lanes' (lanes 0 and 63 load theirs)
+    constexpr bool SHIFT = KX && FULL && kSweepShift;
     static_assert(NS <= kStepStride, "step table too short");
     // the meeting exchange of each pair
     __shared__ T xch[kSweepPairs][4][64];
@@ -163,8 +129,12 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
         r.f = bld<T>(rf, sd.oc, so);
         r.ip = bld<T>(rp, sd.oc, so);
         if constexpr (HAS_X) {
-            r.w = bld<T>(rx, sd.ow, so);
-            r.e = bld<T>(rx, sd.oe, so);
+            if constexpr (SHIFT) {
+                r.w = bld<T>(rx, sd.og, so);   // the segment's edges
+            } else {
+                r.w = bld<T>(rx, sd.ow, so);
+                r.e = bld<T>(rx, sd.oe, so);
+            }
             r.s = bld<T>(rx, sd.os, so);
             r.n = bld<T>(rx, sd.on, so);
             if constexpr (KX) r.c = bld<T>(rx, sd.oc, so);
@@ -173,7 +143,10 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
     };
     auto comb = [&](const Raw<T>& r, const StepCoef<T>& q) -> T {
         T s = r.f;
-        if constexpr (HAS_X) s += q.tl * (r.w + r.e) + q.ts * r.s + q.tn * r.n;
+        if constexpr (SHIFT)
+            s += q.tl * (from_below(r.w, r.c) + from_above(r.w, r.c)) + q.ts * r.s + q.tn * r.n;
+        else if constexpr (HAS_X)
+            s += q.tl * (r.w + r.e) + q.ts * r.s + q.tn * r.n;
         return s;
     };
 

@@ -13,8 +13,6 @@ using namespace dev;
 
 // Two adjacent values (the two longitude children of a coarse column).
 template <typename T>
-using pair_t = T __attribute__((ext_vector_type(2)));
-template <typename T>
 __device__ __forceinline__ pair_t<T> ld2(gcptr base, uint32_t boff) {
     return *(const __attribute__((address_space(1))) pair_t<T>*)(base + boff);
 }
@@ -109,6 +107,158 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
 #pragma unroll
     for (int d = 0; d < DL; ++d)
         if (k0 + d < nz && gc.valid) stb<T>(layer_w(fc, k0 + d, Pcb), oc, out[d]);
+}
+
+// fc = R (f - H x) on the levels that fill the GPU, whose step records cover
+// every layer (nz <= kStepStride). One wavefront per (row-aligned coarse
+// segment, range of LR layers), range-major, walks its layers upward with
+// the loads of the next P layers in flight. The children of a layer serve
+// as the layer above of the step before and the layer below of the step
+// after, so each is loaded once (and one layer below the range). A lane
+// loads, per layer, its two children in each child row (one 2-value load
+// each), the rows south and north of the children, its four longitude
+// neighbours, f and the mass; a row's couplings are its upward step record
+// (Tlam, Ttheta south and north, Tr above), Tr below being the record of
+// the layer before.
+template <typename T>
+struct RestrictWalk;
+template <>
+struct RestrictWalk<float> {
+    static constexpr int LR = 35, P = 3, W = 4;
+};
+template <>
+struct RestrictWalk<double> {
+    static constexpr int LR = 35, P = 2, W = 2;
+};
+// FULLI: every segment has 64 coarse columns (nIc a multiple of 64); then a
+// lane's longitude neighbours are its neighbour lanes' children, and only
+// lanes 0 and 63 load theirs (one load per child row).
+template <typename T, int LR, int P, int W, bool FULLI>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W)))
+void k_restrict_walk(LevelView<T> F, TransferView<T> X, const T* __restrict__ f,
+                     const T* __restrict__ x, T* __restrict__ fc, int wprc, int nsegc,
+                     int units) {
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int unit = int(logical_block()) * (kBlock / 64) + wave;
+    if (unit >= units) return;   // wave-uniform
+    const int rg = unit / nsegc, seg = unit - rg * nsegc;
+    const Seg gc = segment(seg, X.nIc, X.nJc, wprc);
+    const int nI = F.nI, nJ = F.nJ, nz = F.nz;
+    const int Jc = gc.J, Ic = int(gc.c) - Jc * X.nIc;
+    const int j0 = tab(X.child_first, Jc);
+    const int two = tab(X.child_count, Jc) - 1;   // 0 or 1
+    const int j1 = j0 + two;
+    const T w1 = T(two);
+    constexpr uint32_t S = sizeof(T);
+    const uint32_t i0 = 2 * uint32_t(Ic), i1 = i0 + 1;
+    const uint32_t iw = (i0 == 0) ? uint32_t(nI - 1) : i0 - 1;
+    const uint32_t ie = (i1 == uint32_t(nI - 1)) ? 0u : i1 + 1;
+    const uint32_t r0 = uint32_t(j0) * nI, r1 = uint32_t(j1) * nI;
+    const uint32_t rs = (j0 > 0) ? r0 - nI : r0, rn = (j1 < nJ - 1) ? r1 + nI : r1;
+    const uint32_t o0 = (r0 + i0) * S, o1 = (r1 + i0) * S, os = (rs + i0) * S,
+                   on = (rn + i0) * S;
+    const uint32_t ow0 = (r0 + iw) * S, oe0 = (r0 + ie) * S, ow1 = (r1 + iw) * S,
+                   oe1 = (r1 + ie) * S;
+    // lane 0 loads the west edge, lane 63 the east edge, other lanes their
+    // east neighbour (a cache hit; unused)
+    const bool lane0 = (threadIdx.x & 63u) == 0;
+    const uint32_t og0 = lane0 ? ow0 : oe0, og1 = lane0 ? ow1 : oe1;
+    const uint32_t Pb = uint32_t(F.plane) * S, Pcb = uint32_t(X.nIc) * uint32_t(X.nJc) * S;
+    const rsrc_t rx = make_rsrc(x, Pb * uint32_t(nz)), rf = make_rsrc(f, Pb * uint32_t(nz)),
+                 rm = make_rsrc(F.M, Pb * uint32_t(nz)), ro = make_rsrc(fc, Pcb * uint32_t(nz));
+    const StepCoef<T>* q0p = F.sc + size_t(j0) * kStepStride;
+    const StepCoef<T>* q1p = F.sc + size_t(j1) * kStepStride;
+    const uint32_t oc = gc.c * S;
+    const int kb = rg * LR;
+
+    struct Lay {
+        pair_t<T> a, b, xs, xn, fa, fb, ma, mb;
+        T w0, e0, w1, e1;
+        StepCoef<T> q0, q1;
+    };
+    // the loads of step t (layer kb + t, clamped) with its step records;
+    // only the children for the layer above the range
+    auto fetch = [&](int t, bool children_only) {
+        Lay L;
+        const int k = clampk(kb + t, nz);
+        const uint32_t so = uint32_t(k) * Pb;
+        L.a = bld2<T>(rx, o0, so);
+        L.b = bld2<T>(rx, o1, so);
+        if (!children_only) {
+            L.xs = bld2<T>(rx, os, so);
+            L.xn = bld2<T>(rx, on, so);
+            if constexpr (FULLI) {
+                L.w0 = bld<T>(rx, og0, so);   // the edges of the segment's rows
+                L.w1 = bld<T>(rx, og1, so);
+            } else {
+                L.w0 = bld<T>(rx, ow0, so);
+                L.e0 = bld<T>(rx, oe0, so);
+                L.w1 = bld<T>(rx, ow1, so);
+                L.e1 = bld<T>(rx, oe1, so);
+            }
+            L.fa = bld2<T>(rf, o0, so);
+            L.fb = bld2<T>(rf, o1, so);
+            L.ma = bld2<T>(rm, o0, so);
+            L.mb = bld2<T>(rm, o1, so);
+            L.q0 = step_rec(q0p, size_t(k));
+            L.q1 = step_rec(q1p, size_t(k));
+        }
+        return L;
+    };
+
+    // the layer below the range, and its vertical couplings to the first
+    // layer (0 at the bottom)
+    const int kbm = kb > 0 ? kb - 1 : 0;
+    pair_t<T> am = bld2<T>(rx, o0, uint32_t(kbm) * Pb), bm = bld2<T>(rx, o1, uint32_t(kbm) * Pb);
+    const T tbm0 = step_rec(q0p, size_t(kbm)).tc, tbm1 = step_rec(q1p, size_t(kbm)).tc;
+    T tb0 = kb > 0 ? tbm0 : T(0), tb1 = kb > 0 ? tbm1 : T(0);
+    Lay buf[P + 1];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        buf[t] = fetch(t, t == LR);
+    }
+#pragma unroll
+    for (int t = 0; t < LR; ++t) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (t + P <= LR) buf[(t + P) % (P + 1)] = fetch(t + P, t + P == LR);
+        __builtin_amdgcn_sched_barrier(0);
+        const Lay& c = buf[t % (P + 1)];
+        const pair_t<T> ap = buf[(t + 1) % (P + 1)].a, bp = buf[(t + 1) % (P + 1)].b;
+        const StepCoef<T> q0 = c.q0, q1 = c.q1;
+        const pair_t<T> a = c.a, b = c.b, xs = c.xs, xn = c.xn;
+        T w0, e0, w1v, e1;
+        if constexpr (FULLI) {
+            w0 = from_below(c.w0, a.y);
+            e0 = from_above(c.w0, a.x);
+            w1v = from_below(c.w1, b.y);
+            e1 = from_above(c.w1, b.x);
+        } else {
+            w0 = c.w0;
+            e0 = c.e0;
+            w1v = c.w1;
+            e1 = c.e1;
+        }
+        // a merged row's other row is its latitude neighbour
+        const T n00 = two ? b.x : xn.x, n01 = two ? b.y : xn.y;
+        const T s10 = two ? a.x : xs.x, s11 = two ? a.y : xs.y;
+        const T h0 = c.ma.x * a.x + hdiff(q0.tl, q0.ts, q0.tn, a.x, w0, a.y, xs.x, n00) +
+                     c.ma.y * a.y + hdiff(q0.tl, q0.ts, q0.tn, a.y, a.x, e0, xs.y, n01) +
+                     tb0 * ((a.x - am.x) + (a.y - am.y)) +
+                     q0.tc * ((a.x - ap.x) + (a.y - ap.y));
+        const T h1 = c.mb.x * b.x + hdiff(q1.tl, q1.ts, q1.tn, b.x, w1v, b.y, s10, xn.x) +
+                     c.mb.y * b.y + hdiff(q1.tl, q1.ts, q1.tn, b.y, b.x, e1, s11, xn.y) +
+                     tb1 * ((b.x - bm.x) + (b.y - bm.y)) +
+                     q1.tc * ((b.x - bp.x) + (b.y - bp.y));
+        T out = c.fa.x + c.fa.y + w1 * (c.fb.x + c.fb.y) - (h0 + w1 * h1);
+        // computed here, not sunk (with its loads) into the guarded store
+        asm volatile("" : "+v"(out));
+        if (kb + t < nz && gc.valid) bst(out, ro, oc, uint32_t(kb + t) * Pcb);
+        am = a;
+        bm = b;
+        tb0 = q0.tc;
+        tb1 = q1.tc;
+    }
 }
 
 // x += P xc: bilinear interpolation (3/4, 1/4 in longitude; the row weights
@@ -226,7 +376,17 @@ void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T*
     constexpr int waves = kBlock / 64;
     constexpr int DLS = kRestrictLayers;
     constexpr int DLL = std::is_same<T, float>::value ? kRestrictLayersLarge32 : DLS;
-    if (F.plane >= kSmallLevelColumns) {
+    if (x && F.plane >= kSmallLevelColumns && F.nz <= kStepStride) {
+        using C = RestrictWalk<T>;
+        const int units = nsegc * ((F.nz + C::LR - 1) / C::LR);
+        const int nb = (units + waves - 1) / waves;
+        if (X.nIc % 64 == 0)
+            k_restrict_walk<T, C::LR, C::P, C::W, true>
+                <<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
+        else
+            k_restrict_walk<T, C::LR, C::P, C::W, false>
+                <<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
+    } else if (F.plane >= kSmallLevelColumns) {
         const int units = nsegc * ((F.nz + DLL - 1) / DLL);
         const int nb = (units + waves - 1) / waves;
         if (x) k_restrict_seg<T, true, DLL><<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);

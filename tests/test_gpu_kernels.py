@@ -84,3 +84,33 @@ def test_level_kernels(sh, prec, staged):
             ref = x + oracle.prolong(lev, c, xc)
             log(f"  prolong {rel_inf(got, ref):.2e}")
             assert rel_inf(got, ref) < tol
+
+
+# Levels of at least 2^19 columns restrict with the kernel that walks whole
+# ranges of layers (one wavefront per coarse segment and range): ragged
+# coarse widths (550 and 520 columns are not multiples of 64; their lanes
+# load their longitude neighbours), a width of whole segments (512: the
+# neighbours come from the neighbour lanes), and layer counts that are not
+# a multiple of the range.
+LARGE = [shellgen.Shell("wide16", 1100, 480, 16, stretch=1.1),
+         shellgen.Shell("wide37", 1040, 512, 37, stretch=1.05),
+         shellgen.Shell("full16", 1024, 512, 16, stretch=1.1)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("sh", LARGE, ids=[f"{s.nlon}x{s.nlat}x{s.nlev}" for s in LARGE])
+def test_large_level_restriction(sh, prec):
+    a = shellgen.alpha(sh)
+    S = solver_for(sh, a, precision=prec)
+    L = oracle.build_hierarchy(sh, a)
+    assert sh.nlon * sh.nlat >= 1 << 19
+    rng = np.random.default_rng(13)
+    f = rng.standard_normal(sh.shape)
+    x = rng.standard_normal(sh.shape)
+    got = n(S.level_residual_restrict(0, t(f), t(x)))
+    Hx = oracle.apply(L[0], x)
+    ref = oracle.restrict(L[0], L[1], f - Hx)
+    scale = np.abs(oracle.restrict(L[0], L[1], np.abs(f) + np.abs(Hx))).max()
+    err = np.abs(got - ref).max() / scale
+    log(f"{sh.name} {prec}: restrict {err:.2e}")
+    assert err < TOL[prec]

@@ -131,7 +131,7 @@ def test_transposed_vcycle_dot_product_on_gpu():
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-@pytest.mark.parametrize("sh", [SMALL, RAGGED, MEDIUM], ids=lambda s: s.name)
+@pytest.mark.parametrize("sh", [SMALL, RAGGED, DEEP, MEDIUM], ids=lambda s: s.name)
 def test_solve_matches_oracle(sh, prec):
     a = shellgen.alpha(sh)
     b = shellgen.rhs(sh)
