@@ -2,12 +2,13 @@
  * mg.h -- C ABI of the MI355X (gfx950) tensor-product multigrid solver for the
  * anisotropic Helmholtz-type pressure equation on a latitude-longitude shell.
  *
- * The problem (paper, Section 2): solve H u = b, where H is a sparse,
- * Laplacian-like matrix, b a given right-hand side and u the pressure unknowns
- * at grid points. Here H is the cell-centred 7-point finite-volume form of
+ * The problem (paper, Section 2): the linear system H u = b of one
+ * semi-implicit pressure update. The operator is assembled here as the
+ * cell-centred 7-point finite-volume discretisation of
  *     -div(K grad u) + alpha u
- * on a spherical shell, integrated over each cell, with periodic longitude,
- * zero flux across the poles and homogeneous Neumann top and bottom.
+ * on a spherical shell, each row integrated over its cell, with periodic
+ * longitude, zero flux across the poles and homogeneous Neumann top and
+ * bottom; it is symmetric positive definite with seven entries per row.
  *
  * The method (paper, Sections 2.1-2.3): split H = H_z + dH (H_z: diagonal
  * and in-column couplings, dH: horizontal couplings); smooth with damped

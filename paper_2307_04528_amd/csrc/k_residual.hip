@@ -21,24 +21,22 @@ constexpr int kResidualSync = 4;
 constexpr int kResidualTallBlocks = 512;
 constexpr int kResidualTallRows = 16;
 // The walking refinement step: a range of layers per wavefront (the whole
-// column of the 70-layer workloads; 35 or 16 layers on shallower levels),
-// the layers whose loads are in flight ahead of the one being computed, and
-// the rows of a block's tile. Measured on the 1024x768x70 shell (mixed
-// solve, per launch): 446 us with whole columns, 458 us with two ranges of
-// 35 layers; 450 us with 4-row tiles against 458 us with 16-row tiles;
-// loads 2 or 4 layers ahead 467 and 468 us; barriers every 8 layers or
-// none 454 and 459 us; longitude neighbours loaded instead of shifted from
-// the neighbour lanes 489 us.
+// column of the 70-layer workloads; 16 layers on shallow levels), the
+// layers whose loads are in flight ahead of the one being computed, and the
+// same row tiles and barrier interval as above. Measured per launch on the
+// 1024x768x70 shell (mixed solve): 446 us with whole columns against 458 us
+// with two ranges of 35 layers; loads 2 or 4 layers ahead 467 and 468 us
+// against 446; barriers every 8 layers or none 454 and 459 us; longitude
+// neighbours loaded instead of shifted from the neighbour lanes 489 us.
+// 16-row and 4-row tiles are within 1 % there; on 2560x1920x70 16-row
+// tiles take 2.78-2.90 ms against 2.99-3.07 ms (FP64: 3.54-3.59 against
+// 3.82-3.83 ms).
 constexpr int kResidualRange = 70;
-constexpr int kResidualMidRange = 35;
 constexpr int kResidualShortRange = 16;
 constexpr int kResidualAhead = 3;
-constexpr int kResidualWalkRows = 4;
 
 static int residual_walk_range(int nz) {
-    return nz <= kResidualShortRange ? kResidualShortRange
-           : nz <= kResidualMidRange ? kResidualMidRange
-                                     : kResidualRange;
+    return nz <= kResidualShortRange ? kResidualShortRange : kResidualRange;
 }
 
 static int residual_tile_rows(int nI, int nJ) {
@@ -398,10 +396,10 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
     const int nb = residual_update_blocks(L);
     const bool tall = residual_tile_rows(L.nI, L.nJ) == kResidualTallRows;
     if (L.nz <= kStepStride) {
-        const int tiles = tiled_blocks(L.nJ, wpr, kResidualWalkRows);
+        const int tiles = tiled_blocks(L.nJ, wpr, tall ? kResidualTallRows : 4);
         const bool full = L.nI % 64 == 0;
-        auto go = [&](auto lrc, auto fullc) {
-            constexpr int LR = decltype(lrc)::value, R = kResidualWalkRows;
+        auto go = [&](auto lrc, auto rc, auto fullc) {
+            constexpr int LR = decltype(lrc)::value, R = decltype(rc)::value;
             constexpr bool FULLI = decltype(fullc)::value;
             constexpr int P = kResidualAhead, S = kResidualSync;
             if (e)
@@ -411,14 +409,18 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
                 k_residual_walk<TU, TE, TR, false, LR, P, R, S, FULLI>
                     <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
         };
-        auto by_full = [&](auto lrc) {
-            if (full) go(lrc, std::true_type{});
-            else go(lrc, std::false_type{});
+        auto by_rows = [&](auto lrc, auto fullc) {
+            if (tall) go(lrc, std::integral_constant<int, kResidualTallRows>{}, fullc);
+            else go(lrc, std::integral_constant<int, 4>{}, fullc);
         };
-        const int lr = residual_walk_range(L.nz);
-        if (lr == kResidualShortRange) by_full(std::integral_constant<int, kResidualShortRange>{});
-        else if (lr == kResidualMidRange) by_full(std::integral_constant<int, kResidualMidRange>{});
-        else by_full(std::integral_constant<int, kResidualRange>{});
+        auto by_full = [&](auto lrc) {
+            if (full) by_rows(lrc, std::true_type{});
+            else by_rows(lrc, std::false_type{});
+        };
+        if (residual_walk_range(L.nz) == kResidualShortRange)
+            by_full(std::integral_constant<int, kResidualShortRange>{});
+        else
+            by_full(std::integral_constant<int, kResidualRange>{});
         return nb;
     }
     with_nz(L.nz, [&](auto nzc) {
@@ -439,10 +441,10 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
 
 template <typename TU>
 int residual_update_blocks(const LevelView<TU>& L) {
-    const int wpr = segments_per_row(L.nI);
-    if (L.nz > kStepStride) return tiled_blocks(L.nJ, wpr, residual_tile_rows(L.nI, L.nJ));
+    const int tiles = tiled_blocks(L.nJ, segments_per_row(L.nI), residual_tile_rows(L.nI, L.nJ));
+    if (L.nz > kStepStride) return tiles;
     const int lr = residual_walk_range(L.nz);
-    return tiled_blocks(L.nJ, wpr, kResidualWalkRows) * ((L.nz + lr - 1) / lr);
+    return tiles * ((L.nz + lr - 1) / lr);
 }
 
 void sum_partials(const double* partials, int n, double* out, hipStream_t s, int count,

@@ -268,8 +268,8 @@ __device__ __forceinline__ void sweep_segment(const LevelView<T>& L, const T* f,
 // After one block barrier the first two wavefronts solve the twisted
 // factorisation of H_z in rolled loops over LDS (no per-layer address or
 // branch arithmetic of a fully unrolled register solve), with the same
-// arithmetic in the same order as k_smooth: the forward values y_k overwrite
-// s_k, the couplings Tr_next * ip_k overwrite the pivots.
+// recurrences as k_sweep: the forward values y_k overwrite s_k, the
+// couplings Tr_next * ip_k overwrite the pivots.
 constexpr int kStageWaves = 8;
 
 // Dynamic LDS of k_smooth_staged (its static LDS holds NZ + 8 + 256 values).
