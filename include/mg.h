@@ -134,8 +134,17 @@ typedef struct {
  *                 turns the guard off.
  * graphs        : 1 (default): the forward V-cycle below the finest level
  *                 is captured once as a HIP graph (at setup, again when
- *                 options change) and replayed in every cycle; 0: every
- *                 kernel is launched directly. Same kernels and results. */
+ *                 an option it depends on changes: nu_pre, nu_post,
+ *                 coarse_sweeps, omega, precision, smooth_lo, smooth_hi,
+ *                 staged_columns, graphs) and replayed in every cycle; 0:
+ *                 every kernel is launched directly. Same kernels and
+ *                 results.
+ * zero_guess    : 0 (default): u holds the initial guess on entry to a
+ *                 solve. 1: solves start from u = 0 whatever u holds (u is
+ *                 only written), so the first residual is b itself and the
+ *                 first update reads no old iterate. The iterates are those
+ *                 of passing u = 0 with zero_guess = 0 (only the norms of b
+ *                 and of the first residual are summed in another order). */
 typedef struct {
     int32_t levels;
     int32_t nu_pre, nu_post, coarse_sweeps, max_iters;
@@ -148,6 +157,7 @@ typedef struct {
     double stall_factor;
     int32_t stall_iters;
     int32_t graphs;
+    int32_t zero_guess;
 } mg_options;
 
 /* Kernel classes reported by mg_stats when profiling. */

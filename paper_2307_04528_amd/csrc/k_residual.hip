@@ -76,6 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __res
 // of the iterate (FP64; FP32 in the pure single-precision solve):
 //   unew = uin + e (HAS_E; written to uout), r = b - H unew (stored as TR),
 //   per-block partial sums of r^2 in FP64, and of b^2 when partials_b is set.
+// Levels of more than 72 layers (the walking kernel below takes the others).
 template <typename TU, typename TE, typename TR, int NZ, bool HAS_E, int R>
 __global__ __launch_bounds__(64 * R) void k_residual_update(
     LevelView<TU> L, const TU* __restrict__ bv, const TU* __restrict__ uin,
@@ -93,8 +94,9 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
         const uint64_t PU = uint64_t(L.plane) * sizeof(TU),
                        PE = uint64_t(L.plane) * sizeof(TE),
                        PR = uint64_t(L.plane) * sizeof(TR);
+        // uin == nullptr: the iterate before the update is zero
         auto un = [&](int kk, uint32_t ou, uint32_t oe) -> TU {
-            TU v = ldb<TU>(layer(uin, kk, PU), ou);
+            TU v = uin ? ldb<TU>(layer(uin, kk, PU), ou) : TU(0);
             if constexpr (HAS_E) v += TU(ldb<TE>(layer(e, kk, PE), oe));
             return v;
         };
@@ -136,9 +138,11 @@ __global__ __launch_bounds__(64 * R) void k_residual_update(
 // upward step record. FULLI: nI is a multiple of 64, so a lane's longitude
 // neighbours are its neighbour lanes' values, and only lanes 0 and 63 load
 // theirs. Every S layers the block's wavefronts meet at a barrier, so that
-// the latitude neighbours they read are still in L2.
-template <typename TU, typename TE, typename TR, bool HAS_E, int LR, int P, int R, int S,
-          bool FULLI>
+// the latitude neighbours they read are still in L2. HAS_U false: the
+// iterate before the update is zero (the first update of a solve from
+// u = 0), and uin is not read.
+template <typename TU, typename TE, typename TR, bool HAS_E, bool HAS_U, int LR, int P, int R,
+          int S, bool FULLI>
 __global__ __launch_bounds__(64 * R) void k_residual_walk(
     LevelView<TU> L, const TU* __restrict__ bv, const TU* __restrict__ uin,
     const TE* __restrict__ e, TU* __restrict__ uout, TR* __restrict__ r,
@@ -150,7 +154,8 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
     const int nz = L.nz, kb = rg * LR;
     const uint32_t PU = uint32_t(L.plane) * sizeof(TU), PE = uint32_t(L.plane) * sizeof(TE),
                    PR = uint32_t(L.plane) * sizeof(TR);
-    const rsrc_t ru = make_rsrc(uin, PU * uint32_t(nz)), rb = make_rsrc(bv, PU * uint32_t(nz)),
+    const rsrc_t ru = make_rsrc(HAS_U ? uin : bv, PU * uint32_t(nz)),
+                 rb = make_rsrc(bv, PU * uint32_t(nz)),
                  rm = make_rsrc(L.M, PU * uint32_t(nz)),
                  re = make_rsrc(HAS_E ? (const void*)e : (const void*)uin, PE * uint32_t(nz)),
                  rw = make_rsrc(HAS_E ? (const void*)uout : (const void*)uin, PU * uint32_t(nz)),
@@ -164,9 +169,12 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
     const uint32_t rc = g.c * sizeof(TR);
     const StepCoef<TU>* qp = L.sc + size_t(g.J) * kStepStride;
 
-    // u + e at a cell of layer offsets (so_u, so_e)
+    // H is applied to a nonzero iterate (else r = b)
+    constexpr bool HOP = HAS_U || HAS_E;
+    // u + e at a cell of layer offsets (so_u, so_e); u = 0 without HAS_U
     auto un_at = [&](uint32_t ou, uint32_t oe, uint32_t so_u, uint32_t so_e) -> TU {
-        TU v = bld<TU>(ru, ou, so_u);
+        TU v = TU(0);
+        if constexpr (HAS_U) v = bld<TU>(ru, ou, so_u);
         if constexpr (HAS_E) v += TU(bld<TE>(re, oe, so_e));
         return v;
     };
@@ -180,15 +188,18 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
     auto fetch = [&](int t, bool column_only) {
         Lay Q;
         if constexpr (!HAS_E) Q.ec = Q.es = Q.en = Q.ew = Q.ee = TE(0);
+        if constexpr (!HAS_U) Q.uc = Q.us = Q.un = Q.uw = Q.ue = TU(0);
         const int k = clampk(kb + t, nz);
         const uint32_t su = uint32_t(k) * PU, se = uint32_t(k) * PE;
-        Q.uc = bld<TU>(ru, uc, su);
+        if constexpr (HAS_U) Q.uc = bld<TU>(ru, uc, su);
         if constexpr (HAS_E) Q.ec = bld<TE>(re, ec, se);
         if (!column_only) {
-            Q.us = bld<TU>(ru, us, su);
-            Q.un = bld<TU>(ru, un, su);
-            Q.uw = bld<TU>(ru, uw, su);
-            if constexpr (!FULLI) Q.ue = bld<TU>(ru, ue, su);
+            if constexpr (HAS_U) {
+                Q.us = bld<TU>(ru, us, su);
+                Q.un = bld<TU>(ru, un, su);
+                Q.uw = bld<TU>(ru, uw, su);
+                if constexpr (!FULLI) Q.ue = bld<TU>(ru, ue, su);
+            }
             if constexpr (HAS_E) {
                 Q.es = bld<TE>(re, es, se);
                 Q.en = bld<TE>(re, en, se);
@@ -196,13 +207,16 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
                 if constexpr (!FULLI) Q.ee = bld<TE>(re, ee, se);
             }
             Q.b = bld<TU>(rb, uc, su);
-            Q.m = bld<TU>(rm, uc, su);
-            Q.q = step_rec(qp, size_t(k));
+            if constexpr (HOP) {
+                Q.m = bld<TU>(rm, uc, su);
+                Q.q = step_rec(qp, size_t(k));
+            }
         }
         return Q;
     };
     auto sum = [](TU u, TE x) -> TU {
-        if constexpr (HAS_E) return u + TU(x);
+        if constexpr (HAS_U && HAS_E) return u + TU(x);
+        else if constexpr (HAS_E) return TU(x);
         else return u;
     };
 
@@ -237,10 +251,13 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
             xw = sum(c.uw, c.ew);
             xe = sum(c.ue, c.ee);
         }
-        const StepCoef<TU> q = c.q;
-        const TU h = c.m * xc + hdiff(q.tl, q.ts, q.tn, xc, xw, xe, xs, xn) + tb * (xc - um) +
-                     q.tc * (xc - xp);
-        TU rv = c.b - h;
+        TU rv = c.b;
+        if constexpr (HOP) {
+            const StepCoef<TU> q = c.q;
+            rv -= c.m * xc + hdiff(q.tl, q.ts, q.tn, xc, xw, xe, xs, xn) + tb * (xc - um) +
+                  q.tc * (xc - xp);
+            tb = q.tc;
+        }
         // computed here, not sunk (with its loads) into the guarded stores
         asm volatile("" : "+v"(rv));
         const int k = kb + t;
@@ -251,7 +268,6 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
             accb += double(c.b) * double(c.b);
         }
         um = xc;
-        tb = q.tc;
         if (t % S == S - 1) __syncthreads();
     }
     if (partials_b) block_sum2_to(acc, accb, partials + blockIdx.x, partials_b + blockIdx.x);
@@ -402,11 +418,17 @@ int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE
             constexpr int LR = decltype(lrc)::value, R = decltype(rc)::value;
             constexpr bool FULLI = decltype(fullc)::value;
             constexpr int P = kResidualAhead, S = kResidualSync;
-            if (e)
-                k_residual_walk<TU, TE, TR, true, LR, P, R, S, FULLI>
+            if (e && uin)
+                k_residual_walk<TU, TE, TR, true, true, LR, P, R, S, FULLI>
                     <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
-            else
-                k_residual_walk<TU, TE, TR, false, LR, P, R, S, FULLI>
+            else if (e)
+                k_residual_walk<TU, TE, TR, true, false, LR, P, R, S, FULLI>
+                    <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
+            else if (uin)
+                k_residual_walk<TU, TE, TR, false, true, LR, P, R, S, FULLI>
+                    <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
+            else   // r = b: no neighbours (the same blocks and sums as with u = 0)
+                k_residual_walk<TU, TE, TR, false, false, LR, P, R, S, false>
                     <<<nb, 64 * R, 0, s>>>(L, b, uin, e, uout, r, partials, partials_b, wpr, tiles);
         };
         auto by_rows = [&](auto lrc, auto fullc) {

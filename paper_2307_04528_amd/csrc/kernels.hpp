@@ -149,7 +149,10 @@ void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStrea
 //   unew = uin + e (or uin when e == nullptr), written to uout if set;
 //   r = b - H unew, stored as TR; per-block partial sums of r^2 in FP64,
 //   and of b^2 into partials_b when it is not null.
-// Returns the number of blocks (partials written).
+// uin == nullptr stands for a zero iterate (a solve from u = 0): it is not
+// read, and with e == nullptr as well the step is r = b.
+// Returns the number of blocks (partials written): at most
+// max(residual_update_blocks(L), blocks_for(L.plane)).
 template <typename TU, typename TE, typename TR>
 int residual_update(const LevelView<TU>& L, const TU* b, const TU* uin, const TE* e, TU* uout,
                     TR* r, double* partials, double* partials_b, hipStream_t s);

@@ -628,8 +628,11 @@ template <typename T, typename U>
 mg_status refine_step(mg_handle* h, const U* b, const U* uin, const T* e, U* uout, T* r,
                       bool with_bnorm = false) {
     DevLevel& d = h->lv[0];
+    // b read, r written; u and the mass read unless u is zero and stays
+    // so; e read and the new u written when there is an update
     const double bytes =
-        double(d.n) * (3 * sizeof(U) + sizeof(T) + (e ? sizeof(T) + sizeof(U) : 0));
+        double(d.n) * (sizeof(U) + sizeof(T) + (uin ? sizeof(U) : 0) +
+                       (uin || e ? sizeof(U) : 0) + (e ? sizeof(T) + sizeof(U) : 0));
     int nb = 0;
     {
         Phase ph(h, 1);
@@ -664,9 +667,10 @@ mg_status finish_step(mg_handle* h, double* rnorm, double* bnorm = nullptr) {
 // residual in precision U (FP64; FP32 for MG_PREC_FP32, where b and u are
 // cast on entry and u back on exit), with the forward (transposed = false)
 // or transposed V-cycle.
+// zero: start from u = 0 whatever u holds (u is then written only).
 template <typename T, typename U>
 mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* st,
-                bool transposed, bool* stalled = nullptr) {
+                bool transposed, bool zero, bool* stalled = nullptr) {
     if (!(std::is_same<T, float>::value ? h->have32 : h->have64)) {
         // first use of this precision (the FP64 fallback of a mixed solve)
         MG_TRY(ensure_work<T>(h));
@@ -679,9 +683,11 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
     double bnorm = 0;
     const U* bU = nullptr;
     U *ucur = nullptr, *unext = nullptr;
+    // ucur == nullptr: the iterate is zero (a solve from u = 0 before its
+    // first update)
     if constexpr (std::is_same<U, double>::value) {
         bU = b;
-        ucur = u;
+        ucur = zero ? nullptr : u;
     } else {
         if (!h->b32) {
             MG_TRY(dalloc(h, &h->b32, d.n));
@@ -689,14 +695,13 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
             MG_TRY(dalloc(h, &h->u32b, d.n));
         }
         {
-            Launch g(h, MG_K_OTHER, 0, double(d.n) * 24);
+            Launch g(h, MG_K_OTHER, 0, double(d.n) * (zero ? 12 : 24));
             mgk::cast<double, float>(b, h->b32, d.n, h->stream);
-            mgk::cast<double, float>(u, h->u32a, d.n, h->stream);
+            if (!zero) mgk::cast<double, float>(u, h->u32a, d.n, h->stream);
         }
         MG_TRY(check_launch(h, "cast"));
         bU = h->b32;
-        ucur = h->u32a;
-        unext = h->u32b;
+        ucur = zero ? nullptr : h->u32a;
     }
     // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
     T* r = transposed ? w.xbar : w.f;
@@ -752,6 +757,8 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
             // misses.
             if (rn * std::min(rho, 1.0) <= tol * bnorm && ucur != u) unext = u;
             else unext = ucur == h->u_alt ? h->u_alt2 : h->u_alt;
+        } else {
+            unext = ucur == h->u32a ? h->u32b : h->u32a;
         }
         MG_TRY((refine_step<T, U>(h, bU, ucur, e, unext, r)));
         // While the new norm travels to the host, keep the GPU busy with the
@@ -775,7 +782,15 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
             }
         }
     }
-    if constexpr (std::is_same<U, double>::value) {
+    if (!ucur) {
+        // no update was made from u = 0 (b meets the tolerance, or max_iters
+        // is 0): the solution is zero (a fill kernel, not a memset)
+        {
+            Launch g(h, MG_K_OTHER, 0, double(d.n) * 8);
+            mgk::fill<double>(u, 0.0, d.n, h->stream);
+        }
+        MG_TRY(check_launch(h, "fill"));
+    } else if constexpr (std::is_same<U, double>::value) {
         if (ucur != u) {
             Launch g(h, MG_K_OTHER, 0, double(d.n) * 16);
             HIP_TRY(h, hipMemcpyAsync(u, ucur, d.n * sizeof(double), hipMemcpyDeviceToDevice,
@@ -1067,13 +1082,14 @@ mg_status ensure_buffers(mg_handle* h) {
 // stalls continues in FP64 (when fallback is allowed).
 mg_status solve_in_precision(mg_handle* h, const double* rhs, double* u, double tol,
                              mg_stats* st, bool transposed, bool fallback) {
+    const bool zero = h->opt.zero_guess != 0;
     if (h->opt.precision == MG_PREC_FP64)
-        return outer<double, double>(h, rhs, u, tol, st, transposed);
+        return outer<double, double>(h, rhs, u, tol, st, transposed, zero);
     if (h->opt.precision == MG_PREC_FP32)
-        return outer<float, float>(h, rhs, u, tol, st, transposed);
+        return outer<float, float>(h, rhs, u, tol, st, transposed, zero);
     mg_stats s1{};
     bool stalled = false;
-    mg_status s = outer<float, double>(h, rhs, u, tol, &s1, transposed,
+    mg_status s = outer<float, double>(h, rhs, u, tol, &s1, transposed, zero,
                                        fallback ? &stalled : nullptr);
     if (s == MG_OK && stalled) {
         // the FP32 cycle stopped contracting: continue from the current
@@ -1081,7 +1097,7 @@ mg_status solve_in_precision(mg_handle* h, const double* rhs, double* u, double 
         mg_stats s2{};
         const int cap = h->opt.max_iters;
         h->opt.max_iters = cap - s1.iters;
-        s = outer<double, double>(h, rhs, u, tol, &s2, transposed);
+        s = outer<double, double>(h, rhs, u, tol, &s2, transposed, false);
         h->opt.max_iters = cap;
         for (int m = 1; m <= s2.iters && s1.iters + m < MG_HIST; ++m)
             s1.res_hist[s1.iters + m] = s2.res_hist[m];
@@ -1136,6 +1152,7 @@ void mg_options_default(mg_options* o) {
     o->stall_factor = 0.9;
     o->stall_iters = 3;
     o->graphs = 1;
+    o->zero_guess = 0;
 }
 
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,
@@ -1190,6 +1207,15 @@ mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
     if (opts->levels != h->opt.levels || opts->semi_threshold != h->opt.semi_threshold)
         return fail(h, MG_ERR_ARG, "levels and semi_threshold are fixed at setup");
     const bool recoarse = opts->coarse_sweeps != h->dense.sweeps || opts->omega != h->dense.omega;
+    // the captured coarse V-cycle depends on these options only (not on the
+    // stream, the stopping rule, profiling or the initial guess)
+    const mg_options& o = h->opt;
+    const bool recapture =
+        opts->nu_pre != o.nu_pre || opts->nu_post != o.nu_post ||
+        opts->coarse_sweeps != o.coarse_sweeps || opts->omega != o.omega ||
+        opts->precision != o.precision || opts->smooth_lo != o.smooth_lo ||
+        opts->smooth_hi != o.smooth_hi || opts->staged_columns != o.staged_columns ||
+        opts->graphs != o.graphs;
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
     MG_TRY(ensure_buffers(h));
@@ -1197,7 +1223,7 @@ mg_status mg_set_options(mg_handle* h, const mg_options* opts) {
         MG_TRY(rebuild_dense(h));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
     }
-    return capture_graphs(h);
+    return recapture ? capture_graphs(h) : MG_OK;
 }
 
 static mg_status solve_common(mg_handle* h, const double* rhs, double* u, double tol,

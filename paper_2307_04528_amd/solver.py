@@ -50,13 +50,14 @@ def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
 def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, omega=0.8,
              semi_threshold=2.0, precision="mixed", profile=False, stream=None,
              smooth_interval=(1.0 / 3.0, 2.0), staged_columns=65536, stall_factor=0.9,
-             stall_iters=3, graphs=True) -> L.mg_options:
+             stall_iters=3, graphs=True, zero_guess=False) -> L.mg_options:
     """smooth_interval: (lo, hi), per-sweep omegas from the Chebyshev nodes of
     [lo, hi] (the default, see mg.h), or None: every smoothing sweep uses
     omega. staged_columns: levels with fewer columns sweep with the staged
     kernel (0: never). stall_factor, stall_iters: the mixed solve's switch
     to FP64 cycles when it stops contracting (see mg.h). graphs: replay the
-    V-cycle below the finest level as a captured HIP graph."""
+    V-cycle below the finest level as a captured HIP graph. zero_guess: solves
+    start from u = 0 without reading u (Solver.solve sets it per call)."""
     o = L.mg_options()
     L.lib().mg_options_default(C.byref(o))
     o.levels = int(levels)
@@ -74,6 +75,7 @@ def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, ome
     o.staged_columns = int(staged_columns)
     o.stall_factor, o.stall_iters = float(stall_factor), int(stall_iters)
     o.graphs = int(graphs)
+    o.zero_guess = int(bool(zero_guess))
     return o
 
 
@@ -186,6 +188,10 @@ class Solver:
         """The value of one mg_options field in effect for this solver."""
         return getattr(_options(stream=self._stream, **self._opts), name)
 
+    def _zero_guess(self, zero: bool):
+        if bool(self._opts.get("zero_guess", False)) != zero:
+            self.set_options(zero_guess=zero)
+
     def set_options(self, **opts):
         self._opts.update(opts)
         o = _options(stream=self._stream, **self._opts)
@@ -218,9 +224,9 @@ class Solver:
         self._sync_options()
         u = out if out is not None else self._empty()
         self._check(u, "out")
-        if u0 is None:
-            u.zero_()
-        elif u0.data_ptr() != u.data_ptr():
+        # from zero: the library neither reads u nor forms H u for it
+        self._zero_guess(u0 is None)
+        if u0 is not None and u0.data_ptr() != u.data_ptr():
             self._check(u0, "u0")
             u.copy_(u0)
         st = L.mg_stats()
@@ -234,7 +240,8 @@ class Solver:
         """lambda = H^{-T} w with the transposed V-cycle; returns (lambda, stats)."""
         self._check(w, "w")
         self._sync_options()
-        lam = torch.zeros_like(w)
+        self._zero_guess(True)
+        lam = torch.empty_like(w)
         st = L.mg_stats()
         s = L.lib().mg_solve_adjoint(self._h, w.data_ptr(), lam.data_ptr(), float(tol),
                                      C.byref(st))

@@ -12,6 +12,7 @@
     oracle, and central finite differences of L = <w, u>.
 """
 import numpy as np
+import torch
 import pytest
 
 import shellgen
@@ -301,3 +302,51 @@ def test_solve_returns_last_iterate(sh, prec):
         if prec == "fp64":
             ref, _ = oracle.solve(L, b, opt, fixed_iters=st.iters)
             assert rel2(u, ref) < 1e-11, (c, st.iters, rel2(u, ref))
+
+
+NZ128 = shellgen.Shell("nz128", 36, 18, 128, stretch=1.02)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
+@pytest.mark.parametrize("sh", [SMALL, RAGGED, DEEP, NZ128], ids=lambda s: s.name)
+def test_zero_guess_matches_explicit_zero(sh, prec):
+    """zero_guess = 1 (the first residual is b, the first update reads no
+    old iterate) against u = 0 passed in with zero_guess = 0: the same
+    iterations, residual history and solution, bit for bit, whatever the
+    output buffer held; also for the adjoint solve. Shells: rows of whole
+    segments (64x32x16), ragged rows (96 longitudes), 70 layers, and 128
+    layers (the refinement kernel of levels over 72 layers)."""
+    import ctypes as C
+    from paper_2307_04528_amd import _lib as Lb
+    from paper_2307_04528_amd.solver import SolveStats
+    a, b = shellgen.alpha(sh), t(shellgen.rhs(sh))
+    tol = 1e-3 if prec == "fp32" else 1e-9   # FP32 stalls near 1e-4
+    S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+
+    def run(entry, zero, fill):
+        S.set_options(zero_guess=zero)
+        u = S._empty()
+        u.fill_(fill)
+        st = Lb.mg_stats()
+        s = getattr(Lb.lib(), entry)(S._h, b.data_ptr(), u.data_ptr(), float(tol), C.byref(st))
+        # FP32 may stall above the tolerance (MG_ERR_NOT_CONVERGED)
+        assert s in (0, 1), s
+        torch.cuda.synchronize()
+        return u, SolveStats.from_c(st), s
+
+    for entry in ("mg_solve", "mg_solve_adjoint"):
+        u0, st0, s0 = run(entry, False, 0.0)
+        u1, st1, s1 = run(entry, True, float("nan"))   # u's contents are never read
+        log(f"zero guess {sh.name} {prec} {entry}: iters {st1.iters}/{st0.iters} "
+            f"relres {st1.relres:.3e}/{st0.relres:.3e} status {s1}/{s0}")
+        assert s1 == s0
+        assert st1.iters == st0.iters and st1.res_hist == st0.res_hist
+        assert torch.equal(u1, u0)
+    # a right-hand side that already meets the tolerance: no update, u = 0
+    S.set_options(zero_guess=True)
+    u = S._empty().fill_(7.0)
+    st = Lb.mg_stats()
+    z = torch.zeros_like(b)
+    assert Lb.lib().mg_solve(S._h, z.data_ptr(), u.data_ptr(), 1e-8, C.byref(st)) == 0
+    torch.cuda.synchronize()
+    assert st.iters == 0 and torch.count_nonzero(u) == 0

@@ -22,9 +22,11 @@ def test_setup_under_asan_ubsan(tmp_path):
            os.path.join(ROOT, "tests", "setup_sanitize_driver.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+    # verify_asan_link_order=0: the environment may preload other libraries
+    # ahead of the sanitizer runtime; they are left as they are
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
                UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     print(r.stdout)
     assert r.returncode == 0, (r.stdout + r.stderr)[-3000:]
