@@ -1,7 +1,8 @@
 """mg_solve_noalloc, the solve for callers that cannot allocate, against
 mg_solve on the same handle: two calls in a row, the second on a smaller
 grid (the library's scratch keeps the first call's contents), each result
-bit-identical to mg_solve's, with the same iterations and residual."""
+bit-identical to mg_solve's, with the same iterations and residual, from a
+zeroed u and, with zero_guess set, from a u that is never read."""
 import ctypes as C
 
 import numpy as np
@@ -16,8 +17,8 @@ from paper_2307_04528_amd import _lib as L
 pytestmark = pytest.mark.gpu
 
 
-def _noalloc(S, b, tol):
-    u = torch.zeros_like(b)
+def _noalloc(S, b, tol, fill=0.0):
+    u = torch.full_like(b, fill)
     st = L.mg_stats()
     s = L.lib().mg_solve_noalloc(S.handle, b.data_ptr(), u.data_ptr(), float(tol), C.byref(st))
     L.check(s, S.handle, "mg_solve_noalloc")
@@ -44,6 +45,12 @@ def test_noalloc_matches_solve_twice(prec):
         assert st_na.relres <= tol
         assert torch.equal(u_na, u_ref)
         assert st_na.ms_vcycle == 0 and st_na.kern_launches[1] == 0
+        # S.solve left zero_guess set: the no-alloc solve then reads no
+        # initial guess either (u starts as NaN here)
+        assert S.option("zero_guess") == 1
+        u_z, st_z = _noalloc(S, b, tol, fill=float("nan"))
+        assert st_z.iters == st_ref.iters and st_z.relres == st_ref.relres
+        assert torch.equal(u_z, u_ref)
         S.close()
 
 
