@@ -109,8 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
         if (k0 + d < nz && gc.valid) stb<T>(layer_w(fc, k0 + d, Pcb), oc, out[d]);
 }
 
-// fc = R (f - H x) on the levels that fill the GPU, whose step records cover
-// every layer (nz <= kStepStride). One wavefront per (row-aligned coarse
+// fc = R (f - H x) on the larger levels (see RestrictWalk), whose step
+// records cover every layer (nz <= kStepStride). One wavefront per (row-aligned coarse
 // segment, range of LR layers), range-major, walks its layers upward with
 // the loads of the next P layers in flight. The children of a layer serve
 // as the layer above of the step before and the layer below of the step
@@ -120,15 +120,22 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
 // neighbours, f and the mass; a row's couplings are its upward step record
 // (Tlam, Ttheta south and north, Tr above), Tr below being the record of
 // the layer before.
+// Per precision: layers per range, layers in flight ahead, waves per SIMD,
+// and the smallest level (columns) that walks. FP32 on 1024x768x70, per
+// finest-level launch: 171 us with ranges of 10 layers, 175 with 14, 178
+// with 35; on 384x192x70 (73,728 columns) 21 us against 24 us for the
+// chunked kernel, and the whole solve 0.1-0.2 ms faster on both shells.
 template <typename T>
 struct RestrictWalk;
 template <>
 struct RestrictWalk<float> {
-    static constexpr int LR = 35, P = 3, W = 4;
+    static constexpr int LR = 10, P = 3, W = 4;
+    static constexpr long long MinColumns = 1LL << 15;
 };
 template <>
 struct RestrictWalk<double> {
     static constexpr int LR = 35, P = 2, W = 2;
+    static constexpr long long MinColumns = kSmallLevelColumns;
 };
 // FULLI: every segment has 64 coarse columns (nIc a multiple of 64); then a
 // lane's longitude neighbours are its neighbour lanes' children, and only
@@ -376,7 +383,7 @@ void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T*
     constexpr int waves = kBlock / 64;
     constexpr int DLS = kRestrictLayers;
     constexpr int DLL = std::is_same<T, float>::value ? kRestrictLayersLarge32 : DLS;
-    if (x && F.plane >= kSmallLevelColumns && F.nz <= kStepStride) {
+    if (x && F.plane >= RestrictWalk<T>::MinColumns && F.nz <= kStepStride) {
         using C = RestrictWalk<T>;
         const int units = nsegc * ((F.nz + C::LR - 1) / C::LR);
         const int nb = (units + waves - 1) / waves;

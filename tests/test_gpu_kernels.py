@@ -86,15 +86,18 @@ def test_level_kernels(sh, prec, staged):
             assert rel_inf(got, ref) < tol
 
 
-# Levels of at least 2^19 columns restrict with the kernel that walks whole
-# ranges of layers (one wavefront per coarse segment and range): ragged
-# coarse widths (550 and 520 columns are not multiples of 64; their lanes
-# load their longitude neighbours), a width of whole segments (512: the
-# neighbours come from the neighbour lanes), and layer counts that are not
-# a multiple of the range.
+# Larger levels restrict with the kernel that walks ranges of layers (one
+# wavefront per coarse segment and range; FP32 from 2^15 columns, FP64 from
+# 2^19): ragged coarse widths (550, 520 and 100 columns are not multiples
+# of 64; their lanes load their longitude neighbours), widths of whole
+# segments (512 and 128: the neighbours come from the neighbour lanes), and
+# layer counts that are not a multiple of the range (16, 37 and 70 layers
+# against ranges of 10 (FP32) and 35 (FP64)).
 LARGE = [shellgen.Shell("wide16", 1100, 480, 16, stretch=1.1),
          shellgen.Shell("wide37", 1040, 512, 37, stretch=1.05),
-         shellgen.Shell("full16", 1024, 512, 16, stretch=1.1)]
+         shellgen.Shell("full16", 1024, 512, 16, stretch=1.1),
+         shellgen.Shell("mid70", 256, 160, 70, stretch=1.05),
+         shellgen.Shell("mid37", 200, 176, 37, stretch=1.05)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -103,7 +106,7 @@ def test_large_level_restriction(sh, prec):
     a = shellgen.alpha(sh)
     S = solver_for(sh, a, precision=prec)
     L = oracle.build_hierarchy(sh, a)
-    assert sh.nlon * sh.nlat >= 1 << 19
+    assert sh.nlon * sh.nlat >= 1 << 15
     rng = np.random.default_rng(13)
     f = rng.standard_normal(sh.shape)
     x = rng.standard_normal(sh.shape)
