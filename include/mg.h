@@ -32,6 +32,9 @@
  *    MG_ERR_* values < 0 leave outputs unspecified; MG_ERR_NOT_CONVERGED > 0
  *    is a warning (the last iterate is returned). mg_last_error() gives a
  *    human-readable detail of the last failure on a handle.
+ *  - With the environment variable MG_LOG set (and not "0") when a handle is
+ *    set up, its solves print one line per outer iteration to stderr
+ *    (relative residual and contraction factor).
  */
 #ifndef MG_H
 #define MG_H
@@ -144,7 +147,11 @@ typedef struct {
  *                 only written), so the first residual is b itself and the
  *                 first update reads no old iterate. The iterates are those
  *                 of passing u = 0 with zero_guess = 0 (only the norms of b
- *                 and of the first residual are summed in another order). */
+ *                 and of the first residual are summed in another order).
+ * poison        : 1: every floating-point array the library allocates from
+ *                 then on is filled with quiet NaN first (a check that no
+ *                 result depends on memory the library never wrote; costs a
+ *                 fill per allocation). Default 0. */
 typedef struct {
     int32_t levels;
     int32_t nu_pre, nu_post, coarse_sweeps, max_iters;
@@ -158,6 +165,7 @@ typedef struct {
     int32_t stall_iters;
     int32_t graphs;
     int32_t zero_guess;
+    int32_t poison;
 } mg_options;
 
 /* Kernel classes reported by mg_stats when profiling. */

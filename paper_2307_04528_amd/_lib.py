@@ -41,7 +41,7 @@ class mg_options(C.Structure):
                 ("smooth_lo", C.c_double), ("smooth_hi", C.c_double),
                 ("staged_columns", C.c_int32), ("stall_factor", C.c_double),
                 ("stall_iters", C.c_int32), ("graphs", C.c_int32),
-                ("zero_guess", C.c_int32)]
+                ("zero_guess", C.c_int32), ("poison", C.c_int32)]
 
 
 class mg_stats(C.Structure):

@@ -196,6 +196,7 @@ std::string validate(const mg_grid& g, const mg_options& o) {
         return "stall_factor must be finite and > 0, stall_iters >= 0";
     if (o.graphs != 0 && o.graphs != 1) return "graphs must be 0 or 1";
     if (o.zero_guess != 0 && o.zero_guess != 1) return "zero_guess must be 0 or 1";
+    if (o.poison != 0 && o.poison != 1) return "poison must be 0 or 1";
     if (!(o.semi_threshold > 0) || !std::isfinite(o.semi_threshold))
         return "semi_threshold must be finite and > 0";
     if (o.precision != MG_PREC_MIXED && o.precision != MG_PREC_FP64 &&

@@ -18,7 +18,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -114,6 +116,7 @@ struct mg_handle {
     hipStream_t cap_stream = nullptr; // private stream the graphs are captured on
     bool capturing = false;
     bool no_graphs = false;           // replay none (mg_solve_noalloc)
+    bool log = false;                 // MG_LOG set at setup: one line per iteration
     std::string err;
     std::vector<ProfRec> recs;
     std::vector<ProfRec> phases;   // cls 0: a V-cycle, 1: a refinement step
@@ -149,6 +152,8 @@ mg_status fail(mg_handle* h, mg_status s, const char* fmt, ...) {
         if (s_ != MG_OK) return s_;    \
     } while (0)
 
+mg_status check_launch(mg_handle* h, const char* what);
+
 template <typename T>
 mg_status dalloc(mg_handle* h, T** p, size_t count) {
     *p = nullptr;
@@ -162,6 +167,15 @@ mg_status dalloc(mg_handle* h, T** p, size_t count) {
     }
     h->allocs.push_back(q);
     *p = static_cast<T*>(q);
+    // poison: floating-point arrays start as quiet NaN (ordered before any
+    // upload or kernel on the handle's stream), so that a result depending
+    // on memory the library never wrote shows as NaN
+    if constexpr (std::is_same<T, float>::value || std::is_same<T, double>::value) {
+        if (h->opt.poison) {
+            mgk::fill<T>(*p, std::numeric_limits<T>::quiet_NaN(), (long long)count, h->stream);
+            MG_TRY(check_launch(h, "fill"));
+        }
+    }
     return MG_OK;
 }
 
@@ -358,6 +372,10 @@ template <typename T>
 mg_status op_smooth(mg_handle* h, int l, const T* f, const T* xin, T* xout, int cls,
                     double omega) {
     DevLevel& d = h->lv[l];
+    // a Jacobi sweep reads the old iterate of the neighbour columns while
+    // others are written: it must never run in place
+    if (xin == xout || f == xout)
+        return fail(h, MG_ERR_ARG, "internal: sweep on level %d would overwrite its input", l);
     const double bytes = double(d.n) * sizeof(T) * (xin ? 4 : 3);
     {
         Launch g(h, cls, l, bytes);
@@ -772,6 +790,11 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
         std::swap(ucur, unext);
         ++it;
         hist.push_back(rn);
+        if (h->log)
+            std::fprintf(stderr, "mg: %s%s iteration %d relres %.3e factor %.3f\n",
+                         std::is_same<T, float>::value ? "fp32 cycle" : "fp64 cycle",
+                         transposed ? " (adjoint)" : "", it, bnorm > 0 ? rn / bnorm : 0.0,
+                         hist[hist.size() - 2] > 0 ? rn / hist[hist.size() - 2] : 0.0);
         if (!std::isfinite(rn)) status = MG_ERR_BREAKDOWN;
         // stagnation guard: the caller continues with FP64 cycles
         if (stalled && h->opt.stall_iters > 0 && status == MG_OK) {
@@ -1153,6 +1176,7 @@ void mg_options_default(mg_options* o) {
     o->stall_iters = 3;
     o->graphs = 1;
     o->zero_guess = 0;
+    o->poison = 0;
 }
 
 mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_options* opts,
@@ -1167,6 +1191,10 @@ mg_status mg_setup(const mg_grid* grid, const mg_coeffs* coeffs, const mg_option
     h->grid = *grid;
     h->opt = *opts;
     h->stream = static_cast<hipStream_t>(opts->stream);
+    {
+        const char* lg = std::getenv("MG_LOG");
+        h->log = lg && *lg && std::strcmp(lg, "0") != 0;
+    }
     mg_status s = hipGetDevice(&h->device) == hipSuccess ? MG_OK : MG_ERR_HIP;
     if (s == MG_OK) s = init_scratch(h);
     if (s == MG_OK) s = build(h, coeffs->alpha);

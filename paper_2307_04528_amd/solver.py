@@ -50,14 +50,16 @@ def _grid(nlon, nlat, nlev, radius, thickness, stretch, K) -> L.mg_grid:
 def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, omega=0.8,
              semi_threshold=2.0, precision="mixed", profile=False, stream=None,
              smooth_interval=(1.0 / 3.0, 2.0), staged_columns=65536, stall_factor=0.9,
-             stall_iters=3, graphs=True, zero_guess=False) -> L.mg_options:
+             stall_iters=3, graphs=True, zero_guess=False, poison=False) -> L.mg_options:
     """smooth_interval: (lo, hi), per-sweep omegas from the Chebyshev nodes of
     [lo, hi] (the default, see mg.h), or None: every smoothing sweep uses
     omega. staged_columns: levels with fewer columns sweep with the staged
     kernel (0: never). stall_factor, stall_iters: the mixed solve's switch
     to FP64 cycles when it stops contracting (see mg.h). graphs: replay the
     V-cycle below the finest level as a captured HIP graph. zero_guess: solves
-    start from u = 0 without reading u (Solver.solve sets it per call)."""
+    start from u = 0 without reading u (Solver.solve sets it per call).
+    poison: fill the library's floating-point arrays with NaN when allocated
+    (a debugging check)."""
     o = L.mg_options()
     L.lib().mg_options_default(C.byref(o))
     o.levels = int(levels)
@@ -76,6 +78,7 @@ def _options(levels=0, nu_pre=2, nu_post=2, coarse_sweeps=40, max_iters=100, ome
     o.stall_factor, o.stall_iters = float(stall_factor), int(stall_iters)
     o.graphs = int(graphs)
     o.zero_guess = int(bool(zero_guess))
+    o.poison = int(bool(poison))
     return o
 
 

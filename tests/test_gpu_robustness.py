@@ -151,3 +151,66 @@ def test_graph_replays_match_direct_launches(prec):
     ug2, _ = Sg.solve(b, tol=1e-9)
     assert torch.equal(ug2, ud2)
     log(f"graph replays ({prec}): bit-identical over {rep + 1} solves and a re-capture")
+
+
+POISON_SHELLS = [SMALL, shellgen.Shell("ragged", 96, 48, 7, stretch=1.2, thickness=0.05),
+                 shellgen.Shell("deep", 96, 48, 70, stretch=1.05)]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "fp32"])
+@pytest.mark.parametrize("sh", POISON_SHELLS, ids=lambda s: s.name)
+def test_poisoned_allocations_change_nothing(sh, prec):
+    """With every floating-point array of the library NaN-filled when it is
+    allocated (option poison), solves, adjoint solves, V-cycles, the operator
+    and a coefficient update give bit-identical results: nothing the path
+    computes reads memory it did not write first."""
+    a = shellgen.alpha(sh)
+    b = t(shellgen.rhs(sh))
+    w = t(shellgen.weights(sh))
+    tol = 1e-3 if prec == "fp32" else 1e-9
+    kw = dict(precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    Sc, Sp = solver_for(sh, a, **kw), solver_for(sh, a, poison=True, **kw)
+    outs = []
+    for S in (Sc, Sp):
+        o = []
+        u, st = S.solve(b, tol=tol)
+        o += [u, st.iters, st.res_hist]
+        lam, sta = S.solve_adjoint(w, tol=tol)
+        o += [lam, sta.iters]
+        o += [S.vcycle(b), S.vcycle(w, transposed=True), S.apply(u)]
+        S.update_alpha(t(1.1 * a))
+        u2, st2 = S.solve(b, tol=tol, u0=u)
+        o += [u2, st2.iters]
+        torch.cuda.synchronize()
+        outs.append(o)
+    for x, y in zip(*outs):
+        if isinstance(x, torch.Tensor):
+            assert torch.isfinite(y).all()
+            assert torch.equal(x, y)
+        else:
+            assert x == y
+    log(f"poisoned {sh.name} {prec}: bit-identical (iters {outs[1][1]}, {outs[1][4]}, "
+        f"{outs[1][-1]})")
+
+
+def test_mg_log_prints_one_line_per_iteration(capfd, monkeypatch):
+    """MG_LOG set at setup: one stderr line per outer iteration, with the
+    relative residual the solve reports."""
+    sh = SMALL
+    monkeypatch.setenv("MG_LOG", "1")
+    S = solver_for(sh, shellgen.alpha(sh), nu_pre=1, nu_post=1)
+    monkeypatch.delenv("MG_LOG")
+    capfd.readouterr()
+    _, st = S.solve(t(shellgen.rhs(sh)), tol=1e-8)
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("mg: ")]
+    assert len(lines) == st.iters, err
+    last = float(lines[-1].split("relres ")[1].split()[0])
+    assert last == pytest.approx(st.relres, rel=1e-3)
+    # a handle set up without MG_LOG prints nothing
+    Sq = solver_for(sh, shellgen.alpha(sh), nu_pre=1, nu_post=1)
+    capfd.readouterr()
+    Sq.solve(t(shellgen.rhs(sh)), tol=1e-8)
+    torch.cuda.synchronize()
+    assert "mg: " not in capfd.readouterr().err
