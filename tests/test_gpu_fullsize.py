@@ -5,7 +5,8 @@ entry points and launch configuration that bench.py times.
     oracle's, element by element over the whole field; one finest-level
     sweep from an iterate (the benchmark's dominant kernel) and one from
     zero against the oracle's; both sweeps on every coarser level, with and
-    without the staged kernel; the mixed solve to relative residual 1e-8,
+    without the staged kernel; the fused residual-restriction of the two
+    largest levels; the mixed solve to relative residual 1e-8,
     with ||b - H u|| / ||b|| of the returned u recomputed by the oracle on
     the host.
   * shell2560x1920x70 (344M cells): the mixed solve to 1e-8, its residual
@@ -65,6 +66,28 @@ def test_bench_finest_sweeps_full_field():
         f"from an iterate {rel_inf(got, ref):.2e}")
     assert rel_inf(got0, ref0) < 2e-5
     assert rel_inf(got, ref) < 2e-5
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_restriction_full_field(prec):
+    """The fused residual-restriction of the two largest levels of the
+    benchmark hierarchy (the walking kernel, in the launch configuration of
+    the solve), element by element against the oracle's R (f - H x)."""
+    L = bench_levels()
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    for l in (0, 1):
+        rng = np.random.default_rng(200 + l)
+        f = rng.uniform(-1, 1, L[l].shape)
+        x = rng.uniform(-1, 1, L[l].shape)
+        got = n(S.level_residual_restrict(l, t(f), t(x)))
+        Hx = oracle.apply(L[l], x)
+        ref = oracle.restrict(L[l], L[l + 1], f - Hx)
+        scale = np.abs(oracle.restrict(L[l], L[l + 1], np.abs(f) + np.abs(Hx))).max()
+        err = np.abs(got - ref).max() / scale
+        log(f"full-size restriction level {l} {L[l].shape} {prec}: {err:.2e}")
+        assert err < tol
     S.close()
 
 
