@@ -350,3 +350,27 @@ def test_zero_guess_matches_explicit_zero(sh, prec):
     assert Lb.lib().mg_solve(S._h, z.data_ptr(), u.data_ptr(), 1e-8, C.byref(st)) == 0
     torch.cuda.synchronize()
     assert st.iters == 0 and torch.count_nonzero(u) == 0
+
+
+# The layer counts on both sides of the 72-record step tables: 72 layers
+# walk the refinement step in two ranges (70 + 2) and the restriction in
+# ranges of 10 and 35; 73 layers take the kernels that read the coupling
+# tables directly.
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("nz", [72, 73])
+def test_solve_at_the_step_table_boundary(nz, prec):
+    sh = shellgen.Shell(f"nz{nz}", 48, 24, nz, stretch=1.03)
+    a, b = shellgen.alpha(sh), shellgen.rhs(sh)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    # (the FP64 residual of these thin-layered shells stalls near 2e-12)
+    uref, _ = oracle.solve(L, b, opt, tol=5e-12)
+    S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    u, st = S.solve(t(b), tol=1e-11)
+    u = n(u)
+    rel_res = np.linalg.norm((b - oracle.apply(L[0], u)).ravel()) / np.linalg.norm(b)
+    fwd = rel2(u, uref)
+    log(f"nz={nz} {prec}: iters {st.iters} relres {st.relres:.2e} host {rel_res:.2e} "
+        f"fwd {fwd:.2e}")
+    assert st.relres <= 1e-11 and rel_res <= 1.01e-11
+    assert fwd < 1e-8
