@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_seg(LevelView<T> F, Transfe
 // finest-level launch: 171 us with ranges of 10 layers, 175 with 14, 178
 // with 35; on 384x192x70 (73,728 columns) 21 us against 24 us for the
 // chunked kernel, and the whole solve 0.1-0.2 ms faster on both shells.
+// FP64: 303 us with ranges of 10 layers against 320 us with 14 or 35.
 template <typename T>
 struct RestrictWalk;
 template <>
@@ -134,8 +135,8 @@ struct RestrictWalk<float> {
 };
 template <>
 struct RestrictWalk<double> {
-    static constexpr int LR = 35, P = 2, W = 2;
-    static constexpr long long MinColumns = kSmallLevelColumns;
+    static constexpr int LR = 10, P = 2, W = 2;
+    static constexpr long long MinColumns = 1LL << 15;
 };
 // FULLI: every segment has 64 coarse columns (nIc a multiple of 64); then a
 // lane's longitude neighbours are its neighbour lanes' children, and only
@@ -270,12 +271,18 @@ void k_restrict_walk(LevelView<T> F, TransferView<T> X, const T* __restrict__ f,
 
 // x += P xc: bilinear interpolation (3/4, 1/4 in longitude; the row weights
 // of the map in latitude). One wavefront per (row-aligned segment, chunk of
-// kProlongLayers layers), chunk-major so that each XCD streams a band of rows
+// prolong_layers<T>() layers), chunk-major so that each XCD streams a band of rows
 // of one chunk: the fine row's coarse rows and weights are wave-uniform, the
 // per-lane coarse columns are computed once, and the loads of the whole chunk
 // are independent and issued together.
-// (8: 98 us on 1024x768x70, against 115 us with 4 or 16 layers)
+// (FP32 8: 98 us on 1024x768x70, against 115 us with 4 or 16 layers)
 constexpr int kProlongLayers = 8;
+// FP64: 2 layers (245 us against 262 us with 8 and 291 us with 16 on
+// 1024x768x70; its loads take twice the registers)
+template <typename T>
+constexpr int prolong_layers() {
+    return std::is_same<T, float>::value ? kProlongLayers : 2;
+}
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, TransferView<T> X,
                                                         const T* __restrict__ xc,
@@ -296,18 +303,19 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, Transfer
     const uint32_t o1 = uint32_t(J1 * nIc + I) * S, o1n = uint32_t(J1 * nIc + In) * S;
     const uint32_t ox = g.c * S;
     const uint64_t Pb = uint64_t(F.plane) * S, Pcb = uint64_t(nIc) * X.nJc * S;
-    const int nz = F.nz, k0 = ch * kProlongLayers;
+    constexpr int NL = prolong_layers<T>();
+    const int nz = F.nz, k0 = ch * NL;
     const T a = T(0.75), b = T(0.25);
-    T v[kProlongLayers];
+    T v[NL];
 #pragma unroll
-    for (int d = 0; d < kProlongLayers; ++d) {
+    for (int d = 0; d < NL; ++d) {
         const int kk = clampk(k0 + d, nz);
         gcptr ck = layer(xc, kk, Pcb);
         v[d] = ldb<T>(layer(x, kk, Pb), ox) + w0 * (a * ldb<T>(ck, o0) + b * ldb<T>(ck, o0n)) +
                w1 * (a * ldb<T>(ck, o1) + b * ldb<T>(ck, o1n));
     }
 #pragma unroll
-    for (int d = 0; d < kProlongLayers; ++d)
+    for (int d = 0; d < NL; ++d)
         if (k0 + d < nz && g.valid) stb<T>(layer_w(x, k0 + d, Pb), ox, v[d]);
 }
 
@@ -411,7 +419,8 @@ void prolong_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T
                  hipStream_t s) {
     const int wpr = segments_per_row(F.nI);
     const int nseg = F.nJ * wpr;
-    const int units = nseg * ((F.nz + kProlongLayers - 1) / kProlongLayers);
+    constexpr int NL = prolong_layers<T>();
+    const int units = nseg * ((F.nz + NL - 1) / NL);
     constexpr int waves = kBlock / 64;
     k_prolong_add<T><<<(units + waves - 1) / waves, kBlock, 0, s>>>(F, X, xc, x, wpr, nseg,
                                                                     units);

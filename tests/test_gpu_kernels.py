@@ -86,13 +86,12 @@ def test_level_kernels(sh, prec, staged):
             assert rel_inf(got, ref) < tol
 
 
-# Larger levels restrict with the kernel that walks ranges of layers (one
-# wavefront per coarse segment and range; FP32 from 2^15 columns, FP64 from
-# 2^19): ragged coarse widths (550, 520 and 100 columns are not multiples
-# of 64; their lanes load their longitude neighbours), widths of whole
-# segments (512 and 128: the neighbours come from the neighbour lanes), and
-# layer counts that are not a multiple of the range (16, 37 and 70 layers
-# against ranges of 10 (FP32) and 35 (FP64)).
+# Larger levels (from 2^15 columns) restrict with the kernel that walks
+# ranges of 10 layers (one wavefront per coarse segment and range): ragged
+# coarse widths (550, 520 and 100 columns are not multiples of 64; their
+# lanes load their longitude neighbours), widths of whole segments (512 and
+# 128: the neighbours come from the neighbour lanes), and layer counts that
+# are not a multiple of the range (16 and 37 layers).
 LARGE = [shellgen.Shell("wide16", 1100, 480, 16, stretch=1.1),
          shellgen.Shell("wide37", 1040, 512, 37, stretch=1.05),
          shellgen.Shell("full16", 1024, 512, 16, stretch=1.1),
