@@ -85,7 +85,11 @@ struct SegData {
 
 // EX: nz == NZ. FULL: every lane of every wavefront has a column of its
 // own (nI a multiple of 64, nJ of the pairs per block): no store is guarded.
-template <typename T, int NZ, bool EX, bool FULL, bool HAS_X>
+// Levels of at least this many cells store the new iterate with the
+// non-temporal hint; smaller ones keep it in the caches for the next kernel.
+constexpr long long kSweepStreamCells = 1LL << 23;
+
+template <typename T, int NZ, bool EX, bool FULL, bool HAS_X, bool NT>
 __global__ __launch_bounds__(128 * kSweepPairs)
 __attribute__((amdgpu_waves_per_eu(SweepCfg<T, NZ, EX>::W)))
 void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
@@ -234,7 +238,7 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
             else if constexpr (HAS_X) out += keep * xo[c & 1][d];
             int k = top ? nz - 1 - t : t;
             k = k < 0 ? 0 : (k > nz - 1 ? nz - 1 : k);
-            if (own && (FULL || sd.valid)) bst(out, ro, sd.oc, uint32_t(k) * Pb2);
+            if (own && (FULL || sd.valid)) bst<NT>(out, ro, sd.oc, uint32_t(k) * Pb2);
         }
     };
     auto load_x = [&](const SegData<T>& sd, int c, int buf) {
@@ -283,23 +287,31 @@ void sweep(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, hi
     const int wpr = segments_per_row(L.nI);
     constexpr int threads = 128 * kSweepPairs;
     const bool full = L.nI % 64 == 0 && L.nJ % kSweepPairs == 0;
-    auto go = [&](auto nzc, auto exc, auto fullc) {
+    using F = std::false_type;
+    using Tt = std::true_type;
+    auto go = [&](auto nzc, auto exc, auto fullc, auto ntc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr bool EX = decltype(exc)::value, FULL = decltype(fullc)::value;
+        constexpr bool NT = decltype(ntc)::value;
         const int nb = tiled_blocks(L.nJ, wpr, kSweepPairs);
         if (xin)
-            k_sweep<T, NZ, EX, FULL, true><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
+            k_sweep<T, NZ, EX, FULL, true, NT>
+                <<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
         else
-            k_sweep<T, NZ, EX, FULL, false><<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
+            k_sweep<T, NZ, EX, FULL, false, NT>
+                <<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
     };
-    // the workloads' layer counts (70 and 16) exactly, others in buckets
+    // the workloads' layer counts (70 and 16) exactly, others in buckets;
+    // the non-temporal stores on large full levels of those counts
+    const bool stream = L.plane * L.nz >= kSweepStreamCells;
     auto exact = [&](auto nzc) {
-        if (full) go(nzc, std::true_type{}, std::true_type{});
-        else go(nzc, std::true_type{}, std::false_type{});
+        if (!full) go(nzc, Tt{}, F{}, F{});
+        else if (stream) go(nzc, Tt{}, Tt{}, Tt{});
+        else go(nzc, Tt{}, Tt{}, F{});
     };
     if (L.nz == 70) exact(std::integral_constant<int, 70>{});
     else if (L.nz == 16) exact(std::integral_constant<int, 16>{});
-    else with_nz(L.nz, [&](auto nzc) { go(nzc, std::false_type{}, std::false_type{}); });
+    else with_nz(L.nz, [&](auto nzc) { go(nzc, F{}, F{}, F{}); });
 }
 
 template void sweep<float>(const LevelView<float>&, const float*, const float*, float*, float,
