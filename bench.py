@@ -283,10 +283,11 @@ def main():
         log("copy probe: 3 copies of 1 GiB")
 
     t0 = time.perf_counter()
-    # The timed solves carry HIP events around the finest level's sweeps only
-    # (the dominant kernel; profile mode 3): events around every launch add
-    # about half a millisecond per solve. One more, untimed, solve with every
-    # finest-level launch timed gives the per-kernel breakdown.
+    # The timed solves carry one pair of HIP events per V-cycle, around the
+    # finest level's post-smoothing sweeps (the dominant kernel, nu_post
+    # launches in a row; profile mode 3): every event pair between two
+    # kernels idles the GPU for a few microseconds. One more, untimed, solve
+    # with every finest-level launch timed gives the per-kernel breakdown.
     S = Solver.from_shell(sh, alpha, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
                           precision=args.precision, profile=3, smooth_interval=smooth,
                           levels=args.levels, semi_threshold=args.semi_threshold)

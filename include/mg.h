@@ -110,9 +110,10 @@ typedef struct {
  * profile       : 0 = off; 1 = time every finest-level kernel launch with
  *                 HIP events and report per-kernel totals in mg_stats;
  *                 2 = time every launch on every level (adds small gaps);
- *                 3 = time only the finest level's sweeps from an iterate
- *                 (the fewest events, for timing a solve and its dominant
- *                 kernel together).
+ *                 3 = time only the post-smoothing sweeps of each forward
+ *                 V-cycle on the finest level, as one group of nu_post
+ *                 launches (two events per cycle: the fewest, for timing
+ *                 a solve and its dominant kernel together).
  * smooth_lo, smooth_hi: smoothing interval. smooth_lo > 0 (default 1/3,
  *                 2): the nu sweeps of one smoothing step use damping
  *                 factors omega_k = 1/lambda_k, k = 0..nu-1, with lambda_k

@@ -68,6 +68,7 @@ struct ProfRec {
     int cls, level;
     double bytes;
     hipEvent_t a, b;
+    int launches = 1;   // consecutive launches of class cls between a and b
 };
 
 // Explicit matrix C of the coarsest-level solve (x = C f), and C^T for the
@@ -284,10 +285,9 @@ struct Launch {
     Launch(mg_handle* hh, int cls, int level, double bytes) : h(hh) {
         h->alg_bytes += bytes;
         // profile 1: finest level only (no events around the short coarse
-        // launches); 2: every launch
-        // 3: only the finest level's sweeps from an iterate
-        if (!h->opt.profile || (h->opt.profile == 1 && level != 0)) return;
-        if (h->opt.profile == 3 && (level != 0 || cls != MG_K_SMOOTH)) return;
+        // launches); 2: every launch; 3: none (see SweepGroup)
+        if (!h->opt.profile || h->opt.profile == 3 || (h->opt.profile == 1 && level != 0))
+            return;
         rec.cls = cls;
         rec.level = level;
         rec.bytes = bytes;
@@ -299,6 +299,35 @@ struct Launch {
         }
     }
     ~Launch() {
+        if (!on) return;
+        (void)hipEventRecord(rec.b, h->stream);
+        h->recs.push_back(rec);
+    }
+};
+
+// Profile 3: one pair of events around the consecutive post-smoothing
+// sweeps of the finest level in each forward V-cycle, recorded as that many
+// launches of the sweep. Every event pair between two kernels leaves the GPU
+// idle for a few microseconds; two per cycle time the dominant kernel at a
+// quarter of the cost of a pair around each of its launches.
+struct SweepGroup {
+    mg_handle* h;
+    ProfRec rec{};
+    bool on = false;
+    SweepGroup(mg_handle* hh, int level, int launches, double bytes) : h(hh) {
+        if (h->opt.profile != 3 || level != 0 || launches <= 0) return;
+        rec.cls = MG_K_SMOOTH;
+        rec.level = level;
+        rec.bytes = bytes;
+        rec.launches = launches;
+        rec.a = next_event(h);
+        rec.b = next_event(h);
+        if (rec.a && rec.b) {
+            on = true;
+            (void)hipEventRecord(rec.a, h->stream);
+        }
+    }
+    ~SweepGroup() {
         if (!on) return;
         (void)hipEventRecord(rec.b, h->stream);
         h->recs.push_back(rec);
@@ -351,11 +380,11 @@ void prof_collect(mg_handle* h, mg_stats* st) {
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
         st->kern_ms[r.cls] += ms;
         st->kern_bytes[r.cls] += r.bytes;
-        st->kern_launches[r.cls] += 1;
+        st->kern_launches[r.cls] += r.launches;
         if (r.level == 0) {
             st->kern_fine_ms[r.cls] += ms;
             st->kern_fine_bytes[r.cls] += r.bytes;
-            st->kern_fine_launches[r.cls] += 1;
+            st->kern_fine_launches[r.cls] += r.launches;
         }
     }
 }
@@ -471,9 +500,13 @@ mg_status vcycle(mg_handle* h, int l, const T* f, T** result) {
     T* xc = nullptr;
     MG_TRY(vcycle<T>(h, l + 1, wc.f, &xc));
     MG_TRY(op_prolong<T>(h, l, xc, cur));
-    for (int s = 0; s < nu2; ++s) {
-        MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH, mgs::sweep_omega(h->opt, nu2, s)));
-        std::swap(cur, nxt);
+    {
+        SweepGroup g(h, l, nu2, double(nu2) * double(d.n) * sizeof(T) * 4);
+        for (int s = 0; s < nu2; ++s) {
+            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH,
+                                mgs::sweep_omega(h->opt, nu2, s)));
+            std::swap(cur, nxt);
+        }
     }
     *result = cur;
     return MG_OK;

@@ -99,6 +99,41 @@ def test_phase_times():
     assert st.ms_residual < st.ms_vcycle
 
 
+def test_profile_modes_time_without_changing_results():
+    """Profiling only records events: solves with profile 0, 1, 2 and 3 are
+    bit-identical. Profile 0 times nothing; 1 times every finest-level
+    launch; 3 times the post-smoothing sweeps of each forward V-cycle on the
+    finest level as one group of nu_post launches, and its per-launch sweep
+    time is that of profile 1."""
+    sh = shellgen.workload("shell384x192x70")
+    S = solver_for(sh, shellgen.alpha(sh), nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    b = t(shellgen.rhs(sh))
+    res = {}
+    for p in (0, 1, 2, 3):
+        S.set_options(profile=p)
+        u, st = S.solve(b, tol=1e-9)
+        torch.cuda.synchronize()
+        res[p] = (u.clone(), st)
+    u0, st0 = res[0]
+    for p in (1, 2, 3):
+        assert torch.equal(res[p][0], u0), p
+        assert res[p][1].iters == st0.iters and res[p][1].relres == st0.relres, p
+    assert all(k["launches"] == 0 for k in st0.kernels.values())
+    sm1, sm3 = res[1][1].kernels["smooth"], res[3][1].kernels["smooth"]
+    # cycles: one per iteration, and at most one more enqueued ahead in vain
+    cycles = sm3["fine_launches"] // sh.nu_post
+    assert sm3["fine_launches"] == cycles * sh.nu_post
+    assert st0.iters <= cycles <= st0.iters + 1
+    assert sm1["fine_launches"] == cycles * (sh.nu_pre - 1 + sh.nu_post)
+    assert sum(k["launches"] for c, k in res[3][1].kernels.items() if c != "smooth") == 0
+    a1 = sm1["fine_ms"] / sm1["fine_launches"]
+    a3 = sm3["fine_ms"] / sm3["fine_launches"]
+    assert sm3["fine_bytes"] / sm3["fine_launches"] == sm1["fine_bytes"] / sm1["fine_launches"]
+    log(f"sweep per launch: profile 1 {a1 * 1e3:.1f} us, profile 3 {a3 * 1e3:.1f} us "
+        f"({cycles} cycles)")
+    assert 0.7 < a3 / a1 < 1.3
+
+
 def test_autograd_uploads_alpha_after_inplace_change():
     sh = SMALL
     a = t(shellgen.alpha(sh))
