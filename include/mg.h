@@ -195,9 +195,10 @@ enum {
  *               event-timed milliseconds, launches and algorithmic bytes per
  *               kernel class; kern_fine_* the same restricted to the finest
  *               level.
- * ms_vcycle   : device time of the V-cycles (HIP events around each one).
- * ms_residual : device time of the refinement steps (update, residual and
- *               its norm), timed the same way.
+ * ms_vcycle   : with options.profile 1 or 2, device time of the V-cycles
+ *               (HIP events around each one); 0 otherwise.
+ * ms_residual : the same for the refinement steps (update, residual and
+ *               its norm).
  * fell_back_fp64: 1 if the stagnation guard switched a MG_PREC_MIXED solve
  *               to FP64 V-cycles (see mg_options.stall_factor). */
 typedef struct {

@@ -342,12 +342,14 @@ void prof_reset(mg_handle* h) {
 }
 
 // Events around one phase of the outer loop (a V-cycle or a refinement
-// step), summed into mg_stats.ms_vcycle / ms_residual.
+// step), summed into mg_stats.ms_vcycle / ms_residual; with profile 1 and 2
+// only (an event pair between two kernels idles the GPU for microseconds).
 struct Phase {
     mg_handle* h;
     ProfRec rec{};
     bool on = false;
     Phase(mg_handle* hh, int kind) : h(hh) {
+        if (h->opt.profile != 1 && h->opt.profile != 2) return;
         rec.cls = kind;
         rec.a = next_event(h);
         rec.b = next_event(h);

@@ -8,7 +8,8 @@
     stall factor no iteration can beat), the solve continues with FP64
     cycles from its iterate, reports fell_back_fp64 and still meets the
     tolerance and the oracle's solution;
-  * the per-phase device times of a solve are filled in;
+  * the per-phase device times of a solve are filled in with profile 1 and
+    left zero (no events) with profile 0;
   * the autograd wrapper uploads alpha again after an in-place change, and
     not when alpha is unchanged.
 """
@@ -89,8 +90,13 @@ def test_stall_guard_continues_in_fp64():
 
 
 def test_phase_times():
+    """Profile 1 fills in the per-phase device times; profile 0 records
+    no events and leaves them zero."""
     sh = shellgen.workload("shell384x192x70")
     S = solver_for(sh, shellgen.alpha(sh))
+    _, st0 = S.solve(t(shellgen.rhs(sh)), tol=1e-8)
+    assert st0.ms_vcycle == 0 and st0.ms_residual == 0
+    S.set_options(profile=1)
     _, st = S.solve(t(shellgen.rhs(sh)), tol=1e-8)
     log(f"phases: vcycle {st.ms_vcycle:.2f} ms, residual {st.ms_residual:.2f} ms, "
         f"total {st.ms_total:.2f} ms over {st.iters} iterations")
