@@ -177,51 +177,55 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, int(bytes),
                                              0x00020000);
 }
-template <typename T>
-__device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ float bld<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff),
-                                                                          int(soff), 0));
+// Cache policy of the non-temporal hint (bit nt), for loads and stores.
+constexpr int kPolicyNT = 2;
+
+// Loads. NT: with the non-temporal hint, for arrays a kernel reads once per
+// cell and no neighbouring lane or row reads again (a right-hand side, the
+// mass, the pivots), so that they do not take the cache lines of the arrays
+// whose latitude neighbours are read again from L2.
+template <typename T, bool NT = false>
+__device__ __forceinline__ T bld(rsrc_t r, uint32_t voff, uint32_t soff) {
+    constexpr int pol = NT ? kPolicyNT : 0;
+    if constexpr (std::is_same<T, float>::value)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff),
+                                                                              int(soff), pol));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff),
+                                                                               int(soff), pol));
 }
-template <>
-__device__ __forceinline__ double bld<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff),
-                                                                           int(soff), 0));
-}
-// Stores, with the non-temporal hint (cache policy bit nt) unless NT is
-// false. A kernel never reads back what it stores through these; the next
-// kernel reads it. On large levels the hint keeps the written field from
-// evicting the lines still being read; on levels whose fields stay in the
-// caches between kernels it costs the next kernel those hits (measured on
-// the 70-layer shells: sweeps of 14M cells or more 2-7% faster with it,
-// sweeps of 3-5M cells 10-12% slower).
+
+// Stores, with the non-temporal hint unless NT is false. A kernel never
+// reads back what it stores through these; the next kernel reads it. On
+// large levels the hint keeps the written field from evicting the lines
+// still being read; on levels whose fields stay in the caches between
+// kernels it costs the next kernel those hits (measured on the 70-layer
+// shells: sweeps of 14M cells or more 2-7% faster with it, sweeps of 3-5M
+// cells 10-12% slower).
 template <bool NT = true>
 __device__ __forceinline__ void bst(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff),
-                                          int(soff), NT ? 2 : 0);
+                                          int(soff), NT ? kPolicyNT : 0);
 }
 template <bool NT = true>
 __device__ __forceinline__ void bst(double v, rsrc_t r, uint32_t voff, uint32_t soff) {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, int(voff), int(soff),
-                                          NT ? 2 : 0);
+                                          NT ? kPolicyNT : 0);
 }
 
 // Two adjacent values (a lane's two longitude children) with one load.
 template <typename T>
 using pair_t = T __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ pair_t<T> bld2(rsrc_t r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ pair_t<float> bld2<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(pair_t<float>,
-                              __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0));
-}
-template <>
-__device__ __forceinline__ pair_t<double> bld2<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(pair_t<double>,
-                              __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff), 0));
+template <typename T, bool NT = false>
+__device__ __forceinline__ pair_t<T> bld2(rsrc_t r, uint32_t voff, uint32_t soff) {
+    constexpr int pol = NT ? kPolicyNT : 0;
+    if constexpr (std::is_same<T, float>::value)
+        return __builtin_bit_cast(pair_t<float>, __builtin_amdgcn_raw_buffer_load_b64(
+                                                     r, int(voff), int(soff), pol));
+    else
+        return __builtin_bit_cast(pair_t<double>, __builtin_amdgcn_raw_buffer_load_b128(
+                                                      r, int(voff), int(soff), pol));
 }
 
 // Read-only coefficient tables through the constant address space.

@@ -206,9 +206,10 @@ __global__ __launch_bounds__(64 * R) void k_residual_walk(
                 Q.ew = bld<TE>(re, ew, se);
                 if constexpr (!FULLI) Q.ee = bld<TE>(re, ee, se);
             }
-            Q.b = bld<TU>(rb, uc, su);
+            // b and the mass are read at the cell only: non-temporal loads
+            Q.b = bld<TU, true>(rb, uc, su);
             if constexpr (HOP) {
-                Q.m = bld<TU>(rm, uc, su);
+                Q.m = bld<TU, true>(rm, uc, su);
                 Q.q = step_rec(qp, size_t(k));
             }
         }

@@ -204,10 +204,11 @@ void k_restrict_walk(LevelView<T> F, TransferView<T> X, const T* __restrict__ f,
                 L.w1 = bld<T>(rx, ow1, so);
                 L.e1 = bld<T>(rx, oe1, so);
             }
-            L.fa = bld2<T>(rf, o0, so);
-            L.fb = bld2<T>(rf, o1, so);
-            L.ma = bld2<T>(rm, o0, so);
-            L.mb = bld2<T>(rm, o1, so);
+            // f and the mass are read at the children only: non-temporal loads
+            L.fa = bld2<T, true>(rf, o0, so);
+            L.fb = bld2<T, true>(rf, o1, so);
+            L.ma = bld2<T, true>(rm, o0, so);
+            L.mb = bld2<T, true>(rm, o1, so);
             L.q0 = step_rec(q0p, size_t(k));
             L.q1 = step_rec(q1p, size_t(k));
         }
