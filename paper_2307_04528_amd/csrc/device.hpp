@@ -180,6 +180,14 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
 // Cache policy of the non-temporal hint (bit nt), for loads and stores.
 constexpr int kPolicyNT = 2;
 
+// Per-cell fields of at least this many bytes: a kernel's three or four
+// such arrays exceed the 256 MB last-level cache, so nothing it reads once
+// is found there again by the next kernel, and those loads carry the
+// non-temporal hint. On smaller levels the repeated sweeps find their
+// right-hand side there (measured on the 512x384x70 level, 55 MB per FP32
+// field: its sweeps 51 us with plain loads, 61 us with the hint).
+constexpr long long kStreamFieldBytes = 1LL << 26;
+
 // Loads. NT: with the non-temporal hint, for arrays a kernel reads once per
 // cell and no neighbouring lane or row reads again (a right-hand side, the
 // mass, the pivots), so that they do not take the cache lines of the arrays

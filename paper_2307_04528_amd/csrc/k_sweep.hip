@@ -85,12 +85,14 @@ struct SegData {
 
 // EX: nz == NZ. FULL: every lane of every wavefront has a column of its
 // own (nI a multiple of 64, nJ of the pairs per block): no store is guarded.
-// Levels of at least this many cells load the right-hand side and the
-// pivots, and store the new iterate, with the non-temporal hint; smaller
-// ones keep them in the caches for the next kernel.
+// Cache policy CP by level: 0 plain loads and stores; 1 (levels of at
+// least kSweepStreamCells cells) the new iterate stored with the
+// non-temporal hint; 2 (fields of at least kStreamFieldBytes) the
+// right-hand side and the pivots loaded with it as well. Smaller levels keep
+// them in the caches for the next kernel.
 constexpr long long kSweepStreamCells = 1LL << 23;
 
-template <typename T, int NZ, bool EX, bool FULL, bool HAS_X, bool NT>
+template <typename T, int NZ, bool EX, bool FULL, bool HAS_X, int CP>
 __global__ __launch_bounds__(128 * kSweepPairs)
 __attribute__((amdgpu_waves_per_eu(SweepCfg<T, NZ, EX>::W)))
 void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
@@ -105,7 +107,8 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
     constexpr bool SHIFT = KX && FULL && kSweepShift;
     // the FP32 sweep from zero stores with plain stores even on large levels
     // (measured: 1-2% faster solves with it than with the hint)
-    constexpr bool NT_STORE = NT && (HAS_X || !std::is_same<T, float>::value);
+    constexpr bool NT_STORE = CP >= 1 && (HAS_X || !std::is_same<T, float>::value);
+    constexpr bool NT_LOAD = CP >= 2;
     static_assert(NS <= kStepStride, "step table too short");
     // the meeting exchange of each pair
     __shared__ T xch[kSweepPairs][4][64];
@@ -134,8 +137,8 @@ void k_sweep(LevelView<T> L, const T* __restrict__ f, const T* __restrict__ xin,
     auto fetch = [&](const SegData<T>& sd, int t) {
         Raw<T> r;
         const uint32_t so = soff(t);
-        r.f = bld<T, NT>(rf, sd.oc, so);
-        r.ip = bld<T, NT>(rp, sd.oc, so);
+        r.f = bld<T, NT_LOAD>(rf, sd.oc, so);
+        r.ip = bld<T, NT_LOAD>(rp, sd.oc, so);
         if constexpr (HAS_X) {
             if constexpr (SHIFT) {
                 r.w = bld<T>(rx, sd.og, so);   // the segment's edges
@@ -293,29 +296,33 @@ void sweep(const LevelView<T>& L, const T* f, const T* xin, T* xout, T omega, hi
     const bool full = L.nI % 64 == 0 && L.nJ % kSweepPairs == 0;
     using F = std::false_type;
     using Tt = std::true_type;
-    auto go = [&](auto nzc, auto exc, auto fullc, auto ntc) {
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    using P2 = std::integral_constant<int, 2>;
+    auto go = [&](auto nzc, auto exc, auto fullc, auto cpc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr bool EX = decltype(exc)::value, FULL = decltype(fullc)::value;
-        constexpr bool NT = decltype(ntc)::value;
+        constexpr int CP = decltype(cpc)::value;
         const int nb = tiled_blocks(L.nJ, wpr, kSweepPairs);
         if (xin)
-            k_sweep<T, NZ, EX, FULL, true, NT>
+            k_sweep<T, NZ, EX, FULL, true, CP>
                 <<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
         else
-            k_sweep<T, NZ, EX, FULL, false, NT>
+            k_sweep<T, NZ, EX, FULL, false, CP>
                 <<<nb, threads, 0, s>>>(L, f, xin, xout, omega, wpr);
     };
     // the workloads' layer counts (70 and 16) exactly, others in buckets;
-    // the non-temporal stores on large full levels of those counts
-    const bool stream = L.plane * L.nz >= kSweepStreamCells;
+    // the non-temporal hints on large full levels of those counts
+    const long long cells = L.plane * L.nz;
     auto exact = [&](auto nzc) {
-        if (!full) go(nzc, Tt{}, F{}, F{});
-        else if (stream) go(nzc, Tt{}, Tt{}, Tt{});
-        else go(nzc, Tt{}, Tt{}, F{});
+        if (!full) go(nzc, Tt{}, F{}, P0{});
+        else if (cells * (long long)sizeof(T) >= kStreamFieldBytes) go(nzc, Tt{}, Tt{}, P2{});
+        else if (cells >= kSweepStreamCells) go(nzc, Tt{}, Tt{}, P1{});
+        else go(nzc, Tt{}, Tt{}, P0{});
     };
     if (L.nz == 70) exact(std::integral_constant<int, 70>{});
     else if (L.nz == 16) exact(std::integral_constant<int, 16>{});
-    else with_nz(L.nz, [&](auto nzc) { go(nzc, F{}, F{}, F{}); });
+    else with_nz(L.nz, [&](auto nzc) { go(nzc, F{}, F{}, P0{}); });
 }
 
 template void sweep<float>(const LevelView<float>&, const float*, const float*, float*, float,

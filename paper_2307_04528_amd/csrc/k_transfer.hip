@@ -141,7 +141,9 @@ struct RestrictWalk<double> {
 // FULLI: every segment has 64 coarse columns (nIc a multiple of 64); then a
 // lane's longitude neighbours are its neighbour lanes' children, and only
 // lanes 0 and 63 load theirs (one load per child row).
-template <typename T, int LR, int P, int W, bool FULLI>
+// NTL: f and the mass loaded with the non-temporal hint (fields of at least
+// kStreamFieldBytes).
+template <typename T, int LR, int P, int W, bool FULLI, bool NTL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(W)))
 void k_restrict_walk(LevelView<T> F, TransferView<T> X, const T* __restrict__ f,
                      const T* __restrict__ x, T* __restrict__ fc, int wprc, int nsegc,
@@ -204,11 +206,11 @@ void k_restrict_walk(LevelView<T> F, TransferView<T> X, const T* __restrict__ f,
                 L.w1 = bld<T>(rx, ow1, so);
                 L.e1 = bld<T>(rx, oe1, so);
             }
-            // f and the mass are read at the children only: non-temporal loads
-            L.fa = bld2<T, true>(rf, o0, so);
-            L.fb = bld2<T, true>(rf, o1, so);
-            L.ma = bld2<T, true>(rm, o0, so);
-            L.mb = bld2<T, true>(rm, o1, so);
+            // f and the mass are read at the children only
+            L.fa = bld2<T, NTL>(rf, o0, so);
+            L.fb = bld2<T, NTL>(rf, o1, so);
+            L.ma = bld2<T, NTL>(rm, o0, so);
+            L.mb = bld2<T, NTL>(rm, o1, so);
             L.q0 = step_rec(q0p, size_t(k));
             L.q1 = step_rec(q1p, size_t(k));
         }
@@ -396,12 +398,20 @@ void restrict_residual(const LevelView<T>& F, const TransferView<T>& X, const T*
         using C = RestrictWalk<T>;
         const int units = nsegc * ((F.nz + C::LR - 1) / C::LR);
         const int nb = (units + waves - 1) / waves;
-        if (X.nIc % 64 == 0)
-            k_restrict_walk<T, C::LR, C::P, C::W, true>
+        auto go = [&](auto fulli, auto ntl) {
+            k_restrict_walk<T, C::LR, C::P, C::W, decltype(fulli)::value, decltype(ntl)::value>
                 <<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
-        else
-            k_restrict_walk<T, C::LR, C::P, C::W, false>
-                <<<nb, kBlock, 0, s>>>(F, X, f, x, fc, wprc, nsegc, units);
+        };
+        using Tt = std::true_type;
+        using Ff = std::false_type;
+        const bool ntl = F.plane * F.nz * (long long)sizeof(T) >= kStreamFieldBytes;
+        if (X.nIc % 64 == 0) {
+            if (ntl) go(Tt{}, Tt{});
+            else go(Tt{}, Ff{});
+        } else {
+            if (ntl) go(Ff{}, Tt{});
+            else go(Ff{}, Ff{});
+        }
     } else if (F.plane >= kSmallLevelColumns) {
         const int units = nsegc * ((F.nz + DLL - 1) / DLL);
         const int nb = (units + waves - 1) / waves;
