@@ -181,12 +181,14 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
 constexpr int kPolicyNT = 2;
 
 // Per-cell fields of at least this many bytes: a kernel's three or four
-// such arrays exceed the 256 MB last-level cache, so nothing it reads once
-// is found there again by the next kernel, and those loads carry the
-// non-temporal hint. On smaller levels the repeated sweeps find their
-// right-hand side there (measured on the 512x384x70 level, 55 MB per FP32
-// field: its sweeps 51 us with plain loads, 61 us with the hint).
-constexpr long long kStreamFieldBytes = 1LL << 26;
+// such arrays exceed the 256 MB last-level cache at least twice over, so
+// what it reads once is not found there again by the next kernel, and those
+// loads carry the non-temporal hint. On smaller levels the repeated sweeps
+// still find part of their right-hand side there (measured on the
+// 512x504x70 level, 72 MB per FP32 field: its sweeps 51 us with plain
+// loads, 61 us with the hint; the 1024x768x70 solve 1.9% faster with this
+// bound than with 64 MB).
+constexpr long long kStreamFieldBytes = 1LL << 27;
 
 // Loads. NT: with the non-temporal hint, for arrays a kernel reads once per
 // cell and no neighbouring lane or row reads again (a right-hand side, the
