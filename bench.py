@@ -1,11 +1,13 @@
 """Benchmark: time-to-solution of the shell multigrid solve on one MI355X.
 
 One step = one whole solve of H u = b from u = 0 to relative residual 1e-8
-(FP32 V(2,3) cycles inside the FP64 refinement loop) on the 1024x768x70 shell
-(55M unknowns), with b and alpha already resident in HBM. The plain FP64
-multigrid solve of the same system is timed beside it, and every kernel
-launch of the timed region is bracketed by HIP events on the solver's stream
-to give the dominant kernel's achieved bandwidth against the HBM roofline.
+(FP32 V-cycles inside the FP64 refinement loop; the workload's cycle, V(2,4)
+on the 1024x768x70 shell) on the 1024x768x70 shell (55M unknowns), with b
+and alpha already resident in HBM. The plain FP64 multigrid solve of the same
+system is timed beside it, and the finest level's post-smoothing sweeps of
+every V-cycle in the timed region are bracketed by HIP events on the solver's
+stream to give the dominant kernel's achieved bandwidth against the HBM
+roofline.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload NAME]
                     [--no-cpu-baseline] [--no-fp64] [--no-accuracy]
@@ -230,10 +232,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--smooth-interval", default="0.333333333333333333,2", metavar="LO,HI",
+    ap.add_argument("--smooth-interval", default=None, metavar="LO,HI",
                     help="per-sweep damping factors from the Chebyshev nodes of [LO, HI] "
-                         "(default 1/3,2, the library default); 'none': every sweep "
-                         "uses omega 0.8")
+                         "(default: the workload's interval, 1/3,2 unless it names "
+                         "another); 'none': every sweep uses omega 0.8")
     ap.add_argument("--levels", type=int, default=0,
                     help="hierarchy depth: 0 = automatic (default), n = at most n levels "
                          "(the paper's shallow hierarchy is 4)")
@@ -252,9 +254,6 @@ def main():
                          "by 2 %% per step): coefficient update plus a solve warm-started "
                          "from the previous step's solution")
     args = ap.parse_args()
-    smooth = None
-    if args.smooth_interval != "none":
-        smooth = tuple(float(v) for v in args.smooth_interval.split(","))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(no multi-GPU path is built); run with --gpus 1", file=sys.stderr)
@@ -266,6 +265,12 @@ def main():
     from paper_2307_04528_amd import Solver
 
     sh = shellgen.workload(args.workload)
+    if args.smooth_interval is None:
+        smooth = tuple(sh.smooth)
+    elif args.smooth_interval == "none":
+        smooth = None
+    else:
+        smooth = tuple(float(v) for v in args.smooth_interval.split(","))
     dev = torch.device("cuda:0")
     log(f"workload {sh.name}: {sh.nlon}x{sh.nlat}x{sh.nlev} = {sh.n} unknowns")
     alpha = torch.from_numpy(shellgen.alpha(sh)).to(dev)

@@ -46,6 +46,8 @@ class Shell:
                        otherwise alpha = alpha_scale*(1 + 0.5*U[0,1]).
     alpha_scale      : scale of the random alpha field.
     nu_pre, nu_post  : smoothing sweeps the workload's V-cycle uses.
+    smooth           : interval [lo, hi] whose Chebyshev nodes give the
+                       damping factors of the workload's smoothing sweeps.
     tol              : relative residual target of the workload's solve.
     """
     name: str
@@ -60,6 +62,7 @@ class Shell:
     alpha_scale: float = 1e2
     nu_pre: int = 2
     nu_post: int = 2
+    smooth: tuple[float, float] = (1.0 / 3.0, 2.0)
     tol: float = 1e-8
 
     @property
@@ -82,9 +85,14 @@ WORKLOADS: dict[str, Shell] = {
     "shell384x192x70": Shell("shell384x192x70", 384, 192, 70, stretch=1.05),
     # N512-class global grid, 55M unknowns; stretch 1.07 puts the equatorial
     # horizontal-to-vertical spacing ratio near 1e3. Its V-cycle shape is not
-    # fixed by the workload: V(2,3) reaches 1e-8 in 7 iterations (V(2,2): 9).
-    "shell1024x768x70": Shell("shell1024x768x70", 1024, 768, 70, stretch=1.07, nu_post=3),
-    # The operational 10 km grid shape of Table 1: 344M unknowns; V(2,3) as above.
+    # fixed by the workload: V(2,4) with factors from [0.25, 2] reaches 1e-8
+    # in 6 iterations (relres 6.8-7.5e-9 over six alpha and b seeds), V(2,3)
+    # with [1/3, 2] in 7, V(2,2) in 9.
+    "shell1024x768x70": Shell("shell1024x768x70", 1024, 768, 70, stretch=1.07, nu_post=4,
+                              smooth=(0.25, 2.0)),
+    # The operational 10 km grid shape of Table 1: 344M unknowns. V(2,3) with
+    # [1/3, 2] reaches 1e-8 in 7 iterations; V(2,4) with [0.25, 2] also
+    # needs 7 here, so the cheaper cycle stays.
     "shell2560x1920x70": Shell("shell2560x1920x70", 2560, 1920, 70, stretch=1.05, nu_post=3),
 }
 

@@ -28,7 +28,10 @@ def n(x):
 
 
 def solver_for(sh, alpha, **opts):
+    """A handle for shell sh, with the workload's smoothing interval unless
+    opts give another."""
     from paper_2307_04528_amd import Solver
+    opts.setdefault("smooth_interval", sh.smooth)
     log(f"[gpu] setup {sh.nlon}x{sh.nlat}x{sh.nlev} opts={opts}")
     return Solver.from_shell(sh, t(alpha), **opts)
 
@@ -39,7 +42,8 @@ def hierarchy(sh, levels=0):
 
 
 def opts_of(sh, **kw):
-    o = oracle.Options(nu_pre=sh.nu_pre, nu_post=sh.nu_post)
+    o = oracle.Options(nu_pre=sh.nu_pre, nu_post=sh.nu_post, smooth_lo=sh.smooth[0],
+                       smooth_hi=sh.smooth[1])
     for k, v in kw.items():
         setattr(o, k, v)
     return o
