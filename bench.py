@@ -184,6 +184,29 @@ def oracle_solve(shell, tol, smooth, threshold, u_gpu):
             "gpu_vs_oracle": diff}
 
 
+def adjoint_run(S, sh, tol, steps=5):
+    """The adjoint solve lambda = H^-T w (w ~ N(0,1), seeded) with the
+    transposed V-cycle in the same refinement loop, from lambda = 0: median
+    time over `steps` solves after one untimed one."""
+    import torch
+    import shellgen
+    w = torch.from_numpy(shellgen.weights(sh)).to("cuda:0")
+    S.solve_adjoint(w, tol=tol)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        _, st = S.solve_adjoint(w, tol=tol)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    ms = statistics.median(ts) * 1e3
+    log(f"adjoint: {steps} solves, median {ms:.2f} ms, iters {st.iters}, relres {st.relres:.2e}")
+    return {"ms": ms, "iters": st.iters, "relres": st.relres,
+            "ms_per_iteration": ms / max(st.iters, 1),
+            "what": "mg_solve_adjoint of w ~ N(0,1) to the same tolerance: transposed "
+                    "V-cycles inside the FP64 refinement loop, from lambda = 0"}
+
+
 def timestep_run(S, sh, alpha0, b0, steps, tol):
     """Steps 1..steps of shellgen.timestep: per step, the coefficient update
     (masses, pivots, coarsest matrix) and the solve warm-started from the
@@ -249,6 +272,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the forward errors against a reference solution and the "
                          "tolerance sweep")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the timing of the adjoint solve (outside the timed region)")
     ap.add_argument("--timesteps", type=int, default=0, metavar="K",
                     help="also time K steps of a slowly varying sequence (alpha and b drift "
                          "by 2 %% per step): coefficient update plus a solve warm-started "
@@ -387,6 +412,9 @@ def main():
         out["speedup_vs_fp64"] = (total64 / args.steps) / mean_s
         out["mixed_vs_fp64_rel_diff"] = fwd_err(u_mixed, u_fp64)
 
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_run(S, sh, args.tol)
+        out["adjoint"]["forward_ms_per_iteration"] = mean_s * 1e3 / max(st.iters, 1)
     if args.timesteps > 0:
         out["timestep"] = timestep_run(S, sh, alpha, b, args.timesteps, args.tol)
 

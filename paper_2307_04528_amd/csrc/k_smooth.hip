@@ -23,6 +23,10 @@ namespace mgk {
 namespace {
 using namespace dev;
 
+// Rows per block of the one-lane-per-cell kernels (64 columns x this many
+// rows of one layer: each wavefront one row).
+constexpr int kRowsPerBlock = 4;
+
 // Occupancy target of the transposed sweep (waves per SIMD): caps its
 // registers.
 constexpr int kColumnWaves = 2;
@@ -531,11 +535,30 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     }
 }
 
+// Loads and stores of a per-cell array at a layer base, with the
+// non-temporal hint when NT (the policy of the forward sweep on levels of
+// fields of at least kStreamFieldBytes: arrays read or written once per
+// cell).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_pol(gcptr base, uint32_t boff) {
+    const __attribute__((address_space(1))) T* q =
+        (const __attribute__((address_space(1))) T*)(base + boff);
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_pol(gptr base, uint32_t boff, T v) {
+    __attribute__((address_space(1))) T* q = (__attribute__((address_space(1))) T*)(base + boff);
+    if constexpr (NT) __builtin_nontemporal_store(v, q);
+    else *q = v;
+}
+
 // ---------------------------------------------------------------------------
 // Transposed sweep chain kernel:
 //   xb' = HAS_Z ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout)
 //   z = H_z^{-1} xb';  fb = (ACC ? fb : 0) + omega z;  zout = z (if set)
-template <typename T, int NZ, int D, bool HAS_Z, bool ACC>
+// NT: the arrays read or written at the cell only with the non-temporal hint.
+template <typename T, int NZ, int D, bool HAS_Z, bool ACC, bool NT>
 __global__ __launch_bounds__(128 * kPairsPerBlock)
 __attribute__((amdgpu_waves_per_eu(kColumnWaves)))
 void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
@@ -551,7 +574,7 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
     const T keep = T(1) - omega_prev;
     auto fetch = [&](int, int kk) {
         StencilRaw<T> r{};
-        r.f = ldb<T>(layer(xb, kk, Pb), b.c);
+        r.f = ld_pol<NT, T>(layer(xb, kk, Pb), b.c);
         if constexpr (HAS_Z) {
             gcptr zk = layer(zin, kk, Pb);
             r.w = ldb<T>(zk, b.w);
@@ -570,41 +593,50 @@ void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
         }
         return r.f;
     };
-    auto inv = [&](int kk) -> T { return ldb<T>(layer(L.invp, kk, Pb), b.c); };
+    auto inv = [&](int kk) -> T { return ld_pol<NT, T>(layer(L.invp, kk, Pb), b.c); };
     auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
     auto fsink = [&](int, int kk, T s) {
         if constexpr (HAS_Z) {
-            if (g.valid) stb<T>(layer_w(xbout, kk, Pb), b.c, s);
+            if (g.valid) st_pol<NT, T>(layer_w(xbout, kk, Pb), b.c, s);
         }
     };
-    auto bload = [&](int kk) -> T { return ldb<T>(layer(fb, kk, Pb), b.c); };
+    auto bload = [&](int kk) -> T { return ld_pol<NT, T>(layer(fb, kk, Pb), b.c); };
     auto sink = [&](int, int kk, T z, T e) {
         T fo = omega * z;
         if constexpr (ACC) fo += e;
         if (g.valid) {
-            if (zout) stb<T>(layer_w(zout, kk, Pb), b.c, z);
-            stb<T>(layer_w(fb, kk, Pb), b.c, fo);
+            if (zout) st_pol<NT, T>(layer_w(zout, kk, Pb), b.c, z);
+            st_pol<NT, T>(layer_w(fb, kk, Pb), b.c, fo);
         }
     };
     twisted_column<T, NZ, D, ACC>(L.nz, p.top, xch[p.pair], fetch, comb, inv, cpl, fsink, bload,
                                   sink);
 }
 
-// xb = (1-omega) xb + omega sum_h T_h z_nb, one lane per cell.
+// xb = (1-omega) xb + omega sum_h T_h z_nb, one lane per cell. Blocks of
+// 64 columns x kRowsPerBlock rows of one layer (grid: column groups, row
+// groups, layers): a wavefront takes part of one row of one layer, so the
+// row's couplings are wave-uniform and no lane divides its index.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adjoint_stencil(LevelView<T> L,
-                                                            const T* __restrict__ z,
-                                                            T* __restrict__ xb, T omega,
-                                                            uint32_t n) {
-    const uint32_t t = global_index();
-    if (t >= n) return;
-    const uint32_t P = uint32_t(L.plane);
-    const int k = int(t / P);
-    const Nb b = neighbours<false>(t - uint32_t(k) * P, L.nI, L.nJ);
-    const int nJ = L.nJ;
-    const T* zk = z + size_t(k) * P;
-    const T h = L.Tlam[k * nJ + b.J] * (zk[b.w] + zk[b.e]) + L.Tth[k * (nJ + 1) + b.J] * zk[b.s] +
-                L.Tth[k * (nJ + 1) + b.J + 1] * zk[b.n];
+__global__ __launch_bounds__(64 * kRowsPerBlock) void k_adjoint_stencil(LevelView<T> L,
+                                                                        const T* __restrict__ z,
+                                                                        T* __restrict__ xb,
+                                                                        T omega) {
+    const int nI = L.nI, nJ = L.nJ;
+    const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
+    const int J = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
+                                                 int(threadIdx.y));
+    const int k = int(blockIdx.z);
+    if (i >= nI || J >= nJ) return;
+    const uint32_t col = uint32_t(J) * uint32_t(nI) + uint32_t(i);
+    const uint32_t w = (i == 0) ? col + uint32_t(nI - 1) : col - 1u;
+    const uint32_t e = (i == nI - 1) ? col - uint32_t(nI - 1) : col + 1u;
+    const uint32_t sn = (J > 0) ? col - uint32_t(nI) : col;
+    const uint32_t nn = (J < nJ - 1) ? col + uint32_t(nI) : col;
+    const T* zk = z + size_t(k) * size_t(L.plane);
+    const size_t t = size_t(k) * size_t(L.plane) + col;
+    const T h = L.Tlam[k * nJ + J] * (zk[w] + zk[e]) + L.Tth[k * (nJ + 1) + J] * zk[sn] +
+                L.Tth[k * (nJ + 1) + J + 1] * zk[nn];
     xb[t] = (T(1) - omega) * xb[t] + omega * h;
 }
 
@@ -702,25 +734,36 @@ void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout
     const int wpr = segments_per_row(L.nI);
     const int nb = pair_blocks<T>(L.nJ, wpr);
     constexpr int threads = 128 * kPairsPerBlock;
+    const bool stream = L.plane * L.nz * (long long)sizeof(T) >= kStreamFieldBytes;
     with_nz(L.nz, [&](auto nzc) {
         constexpr int NZ = decltype(nzc)::value;
         constexpr int D = ChunkDepth<T>::value;
-#define MG_SMOOTHT_LAUNCH(HZ, AC)                                                          \
-    k_smooth_T<T, NZ, D, HZ, AC><<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega_prev, \
-                                                       omega, wpr)
+        auto go = [&](auto hz, auto ac, auto nt) {
+            k_smooth_T<T, NZ, D, decltype(hz)::value, decltype(ac)::value, decltype(nt)::value>
+                <<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega_prev, omega, wpr);
+        };
+        auto pick = [&](auto hz, auto ac) {
+            // the hinted variant for the 70-layer bucket only
+            if constexpr (NZ == 72) {
+                if (stream) return go(hz, ac, std::true_type{});
+            }
+            go(hz, ac, std::false_type{});
+        };
+        using Tt = std::true_type;
+        using Ff = std::false_type;
         if (zin) {
-            if (accumulate) MG_SMOOTHT_LAUNCH(true, true); else MG_SMOOTHT_LAUNCH(true, false);
+            if (accumulate) pick(Tt{}, Tt{}); else pick(Tt{}, Ff{});
         } else {
-            if (accumulate) MG_SMOOTHT_LAUNCH(false, true); else MG_SMOOTHT_LAUNCH(false, false);
+            if (accumulate) pick(Ff{}, Tt{}); else pick(Ff{}, Ff{});
         }
-#undef MG_SMOOTHT_LAUNCH
     });
 }
 
 template <typename T>
 void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s) {
-    const long long n = L.plane * L.nz;
-    k_adjoint_stencil<T><<<blocks_for(n), kBlock, 0, s>>>(L, z, xb, omega, uint32_t(n));
+    const dim3 grid(unsigned((L.nI + 63) / 64), unsigned((L.nJ + kRowsPerBlock - 1) / kRowsPerBlock),
+                    unsigned(L.nz));
+    k_adjoint_stencil<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(L, z, xb, omega);
 }
 
 bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int sweeps,

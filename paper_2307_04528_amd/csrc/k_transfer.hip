@@ -11,6 +11,10 @@ namespace mgk {
 namespace {
 using namespace dev;
 
+// Rows per block of the one-lane-per-cell kernels (64 columns x this many
+// rows of one layer: each wavefront one row).
+constexpr int kRowsPerBlock = 4;
+
 // Two adjacent values (the two longitude children of a coarse column).
 template <typename T>
 __device__ __forceinline__ pair_t<T> ld2(gcptr base, uint32_t boff) {
@@ -324,16 +328,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, Transfer
 
 // xc = P^T x, one lane per coarse cell.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_T(LevelView<T> F, TransferView<T> X,
-                                                      const T* __restrict__ x,
-                                                      T* __restrict__ xc, uint32_t nc) {
-    const uint32_t t = global_index();
-    if (t >= nc) return;
-    const uint32_t Pc = uint32_t(X.nIc) * X.nJc;
-    const int k = int(t / Pc);
-    const uint32_t colc = t - uint32_t(k) * Pc;
-    const int Jc = int(colc / uint32_t(X.nIc));
-    const int Ic = int(colc) - Jc * X.nIc;
+__global__ __launch_bounds__(64 * kRowsPerBlock) void k_prolong_T(LevelView<T> F,
+                                                                  TransferView<T> X,
+                                                                  const T* __restrict__ x,
+                                                                  T* __restrict__ xc) {
+    // blocks of 64 coarse columns x kRowsPerBlock coarse rows of one layer
+    const int Ic = int(blockIdx.x) * 64 + int(threadIdx.x);
+    const int Jc = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
+                                                  int(threadIdx.y));
+    const int k = int(blockIdx.z);
+    if (Ic >= X.nIc || Jc >= X.nJc) return;
+    const size_t t = (size_t(k) * X.nJc + size_t(Jc)) * X.nIc + size_t(Ic);
     const int nIf = F.nI;
     const int iE = 2 * Ic, iO = 2 * Ic + 1;
     const int iW = (iE == 0) ? nIf - 1 : iE - 1;
@@ -351,21 +356,19 @@ __global__ __launch_bounds__(kBlock) void k_prolong_T(LevelView<T> F, TransferVi
 }
 
 // fb += y, xb -= H y with y = R^T fcb (every child takes its coarse value),
-// one lane per fine cell.
+// one lane per fine cell, in blocks of 64 columns x kRowsPerBlock rows of one
+// layer (the row's couplings and coarse rows wave-uniform).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_inject_residual_adj(LevelView<T> F,
-                                                                TransferView<T> X,
-                                                                const T* __restrict__ fcb,
-                                                                T* __restrict__ xb,
-                                                                T* __restrict__ fb, uint32_t n) {
-    const uint32_t t = global_index();
-    if (t >= n) return;
-    const uint32_t P = uint32_t(F.plane);
+__global__ __launch_bounds__(64 * kRowsPerBlock) void k_inject_residual_adj(
+    LevelView<T> F, TransferView<T> X, const T* __restrict__ fcb, T* __restrict__ xb,
+    T* __restrict__ fb) {
     const int nI = F.nI, nJ = F.nJ, nz = F.nz, nIc = X.nIc;
-    const int k = int(t / P);
-    const uint32_t col = t - uint32_t(k) * P;
-    const int j = int(col / uint32_t(nI));
-    const int i = int(col) - j * nI;
+    const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
+    const int j = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
+                                                 int(threadIdx.y));
+    const int k = int(blockIdx.z);
+    if (i >= nI || j >= nJ) return;
+    const size_t t = size_t(k) * size_t(F.plane) + size_t(j) * size_t(nI) + size_t(i);
     const size_t Pc = size_t(nIc) * X.nJc;
     const int iw = (i == 0) ? nI - 1 : i - 1, ie = (i == nI - 1) ? 0 : i + 1;
     const int oc = X.crow_of[j] * nIc;
@@ -440,15 +443,17 @@ void prolong_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T
 template <typename T>
 void prolong_transpose(const LevelView<T>& F, const TransferView<T>& X, const T* x, T* xc,
                        hipStream_t s) {
-    const long long nc = (long long)X.nIc * X.nJc * F.nz;
-    k_prolong_T<T><<<blocks_for(nc), kBlock, 0, s>>>(F, X, x, xc, uint32_t(nc));
+    const dim3 grid(unsigned((X.nIc + 63) / 64),
+                    unsigned((X.nJc + kRowsPerBlock - 1) / kRowsPerBlock), unsigned(F.nz));
+    k_prolong_T<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, x, xc);
 }
 
 template <typename T>
 void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X, const T* fcb,
                              T* xb, T* fb, hipStream_t s) {
-    const long long n = F.plane * F.nz;
-    k_inject_residual_adj<T><<<blocks_for(n), kBlock, 0, s>>>(F, X, fcb, xb, fb, uint32_t(n));
+    const dim3 grid(unsigned((F.nI + 63) / 64), unsigned((F.nJ + kRowsPerBlock - 1) / kRowsPerBlock),
+                    unsigned(F.nz));
+    k_inject_residual_adj<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, fcb, xb, fb);
 }
 
 #define MG_INST(T)                                                                       \
