@@ -408,6 +408,141 @@ __global__ __launch_bounds__(64 * kStageWaves) void k_smooth_staged(
     }
 }
 
+// The transposed chain kernel (k_smooth_T) on a small level, staged like
+// k_smooth_staged: eight wavefronts form xb' = (1-omega_prev) xb + omega_prev
+// sum_h T_h zin_nb (HAS_Z; else xb' = xb, and xbout is not written) and stage
+// it with the pivots and, with ACC, the old fb in LDS; one pair solves
+// H_z z = xb' (H_z is symmetric: the forward twisted solve) and writes
+// zout = z and fb = (ACC ? fb : 0) + omega z.
+template <typename T, int NZ, bool ACC>
+constexpr size_t staged_T_lds_bytes() {
+    return sizeof(T) * size_t(ACC ? 3 : 2) * NZ * 64;
+}
+
+template <typename T, int NZ, bool HAS_Z, bool ACC>
+__global__ __launch_bounds__(64 * kStageWaves) void k_smooth_T_staged(
+    LevelView<T> L, const T* xb, const T* __restrict__ zin, T* xbout, T* __restrict__ zout,
+    T* __restrict__ fb, T omega_prev, T omega, int wpr) {
+    extern __shared__ unsigned char smem_raw[];
+    T* ls = reinterpret_cast<T*>(smem_raw);   // [NZ][64] xb'_k, then y_k
+    T* lp = ls + NZ * 64;                      // [NZ][64] ip_k, then cb_k
+    T* lf = lp + NZ * 64;                      // [NZ][64] old fb (ACC)
+    __shared__ T ltr[NZ + 8];   // Tr_F of the row
+    __shared__ T xch[256];      // the pair's exchange
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int lane = int(threadIdx.x & 63u);
+    const Seg g = segment(int(blockIdx.x), L.nI, L.nJ, wpr);
+    const NbB<T> b(g);
+    const int nz = L.nz, nJ = L.nJ, J = g.J;
+    const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
+    constexpr int Q = (NZ + kStageWaves - 1) / kStageWaves;
+    const T keep = T(1) - omega_prev;
+    {
+        const int F = int(threadIdx.x);
+        const T trF = F <= nz ? L.Tr[size_t(F) * size_t(nJ) + size_t(J)] : T(0);
+        T ctl = T(0), cts = T(0), ctn = T(0);
+        if (HAS_Z && lane < Q) {
+            const int kq = clampk(wave + lane * kStageWaves, nz);
+            ctl = L.Tlam[size_t(kq) * size_t(nJ) + size_t(J)];
+            cts = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J)];
+            ctn = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J) + 1];
+        }
+        T rb[Q], rp[Q], rf[ACC ? Q : 1], rw[HAS_Z ? Q : 1], re[HAS_Z ? Q : 1],
+            rs[HAS_Z ? Q : 1], rn[HAS_Z ? Q : 1];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int kk = clampk(wave + q * kStageWaves, nz);
+            rb[q] = ldb<T>(layer(xb, kk, Pb), b.c);
+            rp[q] = ldb<T>(layer(L.invp, kk, Pb), b.c);
+            if constexpr (ACC) rf[q] = ldb<T>(layer(fb, kk, Pb), b.c);
+            if constexpr (HAS_Z) {
+                gcptr zl = layer(zin, kk, Pb);
+                rw[q] = ldb<T>(zl, b.w);
+                re[q] = ldb<T>(zl, b.e);
+                rs[q] = ldb<T>(zl, b.s);
+                rn[q] = ldb<T>(zl, b.n);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (F <= nz) ltr[F] = trF;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = wave + q * kStageWaves;
+            if (k < nz) {
+                T sv = rb[q];
+                if constexpr (HAS_Z) {
+                    const T h = lane_value(ctl, q) * (rw[q] + re[q]) + lane_value(cts, q) * rs[q] +
+                                lane_value(ctn, q) * rn[q];
+                    sv = keep * rb[q] + omega_prev * h;
+                    // every lane has read its own xb of this layer (xbout may be xb)
+                    if (g.valid) stb<T>(layer_w(xbout, k, Pb), b.c, sv);
+                }
+                ls[k * 64 + lane] = sv;
+                lp[k * 64 + lane] = rp[q];
+                if constexpr (ACC) lf[k * 64 + lane] = rf[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (wave >= 2) {
+        __syncthreads();   // the solving pair's exchange barrier
+        return;
+    }
+    const bool top = wave == 1;
+    const int m = nz >> 1;
+    T vp = T(0), sm = T(0), im = T(0);
+    if (!top) {
+#pragma unroll 4
+        for (int k = 0; k < m; ++k) {
+            const T sv = ls[k * 64 + lane], ip = lp[k * 64 + lane];
+            const T v = (sv + ltr[k] * vp) * ip;
+            ls[k * 64 + lane] = v;
+            lp[k * 64 + lane] = ltr[k + 1] * ip;
+            vp = v;
+        }
+        xch[lane] = vp;
+    } else {
+#pragma unroll 4
+        for (int k = nz - 1; k > m; --k) {
+            const T sv = ls[k * 64 + lane], ip = lp[k * 64 + lane];
+            const T v = (sv + ltr[k + 1] * vp) * ip;
+            ls[k * 64 + lane] = v;
+            lp[k * 64 + lane] = ltr[k] * ip;
+            vp = v;
+        }
+        sm = ls[m * 64 + lane];
+        im = lp[m * 64 + lane];
+        xch[64 + lane] = vp;
+        xch[128 + lane] = sm;
+        xch[192 + lane] = im;
+    }
+    __syncthreads();
+    const T zm =
+        (xch[128 + lane] + ltr[m] * xch[lane] + ltr[m + 1] * xch[64 + lane]) * xch[192 + lane];
+    auto put = [&](int k, T z) {
+        if (!g.valid) return;
+        if (zout) stb<T>(layer_w(zout, k, Pb), b.c, z);
+        T fo = omega * z;
+        if constexpr (ACC) fo += lf[k * 64 + lane];
+        stb<T>(layer_w(fb, k, Pb), b.c, fo);
+    };
+    T zv = zm;
+    if (!top) {
+#pragma unroll 4
+        for (int k = m - 1; k >= 0; --k) {
+            zv = ls[k * 64 + lane] + lp[k * 64 + lane] * zv;
+            put(k, zv);
+        }
+    } else {
+        put(m, zm);
+#pragma unroll 4
+        for (int k = m + 1; k < nz; ++k) {
+            zv = ls[k * 64 + lane] + lp[k * 64 + lane] * zv;
+            put(k, zv);
+        }
+    }
+}
+
 // The coarsest level in one launch from global memory: one block does every
 // sweep from zero, segment by segment, ping-ponging between xa and xb, with
 // a block barrier between sweeps (the global writes of a sweep are visible
@@ -728,9 +863,52 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
     return (sweeps & 1) ? 0 : 1;
 }
 
+// The staged transposed chain kernel on a small level; false where the level
+// is not small or the staging buffers do not fit in LDS.
+template <typename T>
+bool launch_staged_T(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
+                     T* fb, T omega_prev, T omega, bool accumulate, long long staged_columns,
+                     hipStream_t s) {
+    if (L.plane >= staged_columns) return false;
+    const int wpr = segments_per_row(L.nI);
+    const int nb = L.nJ * wpr;
+    bool launched = false;
+    with_nz(L.nz, [&](auto nzc) {
+        constexpr int NZ = decltype(nzc)::value;
+        auto go = [&](auto hz, auto ac) {
+            constexpr bool HZ = decltype(hz)::value, AC = decltype(ac)::value;
+            constexpr size_t lds = staged_T_lds_bytes<T, NZ, AC>();
+            if constexpr (lds + sizeof(T) * (NZ + 8 + 256) <= kMaxLds) {
+                const void* fn = reinterpret_cast<const void*>(&k_smooth_T_staged<T, NZ, HZ, AC>);
+                if (lds > 64 * 1024 &&
+                    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(lds)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return;
+                }
+                k_smooth_T_staged<T, NZ, HZ, AC><<<nb, 64 * kStageWaves, lds, s>>>(
+                    L, xb, zin, xbout, zout, fb, omega_prev, omega, wpr);
+                launched = true;
+            }
+        };
+        using Tt = std::true_type;
+        using Ff = std::false_type;
+        if (zin) {
+            if (accumulate) go(Tt{}, Tt{}); else go(Tt{}, Ff{});
+        } else {
+            if (accumulate) go(Ff{}, Tt{}); else go(Ff{}, Ff{});
+        }
+    });
+    return launched;
+}
+
 template <typename T>
 void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
-                      T* fb, T omega_prev, T omega, bool accumulate, hipStream_t s) {
+                      T* fb, T omega_prev, T omega, bool accumulate, long long staged_columns,
+                      hipStream_t s) {
+    if (launch_staged_T<T>(L, xb, zin, xbout, zout, fb, omega_prev, omega, accumulate,
+                           staged_columns, s))
+        return;
     const int wpr = segments_per_row(L.nI);
     const int nb = pair_blocks<T>(L.nJ, wpr);
     constexpr int threads = 128 * kPairsPerBlock;
@@ -779,7 +957,7 @@ bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int swee
     template int coarse_solve<T>(const LevelView<T>&, const T*, T*, T*, T, int, size_t,       \
                                  hipStream_t);                                              \
     template void smooth_transpose<T>(const LevelView<T>&, const T*, const T*, T*, T*, T*, \
-                                      T, T, bool, hipStream_t);                             \
+                                      T, T, bool, long long, hipStream_t);                  \
     template void adjoint_stencil<T>(const LevelView<T>&, const T*, T*, T, hipStream_t);
 MG_INST(float)
 MG_INST(double)

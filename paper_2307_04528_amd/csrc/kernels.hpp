@@ -136,9 +136,11 @@ void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X,
 //   xb' = zin ? (1-omega_prev) xb + omega_prev sum_h T_h zin_nb : xb
 //         (-> xbout if set)
 //   z   = H_z^{-1} xb';  fb = (accumulate ? fb : 0) + omega z;  zout = z if set.
+// Levels of fewer than staged_columns columns use the staged kernel.
 template <typename T>
 void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout,
-                      T* zout, T* fb, T omega_prev, T omega, bool accumulate, hipStream_t s);
+                      T* zout, T* fb, T omega_prev, T omega, bool accumulate,
+                      long long staged_columns, hipStream_t s);
 
 // xb = (1-omega) xb + omega sum_h T_h z_nb (in place on xb).
 template <typename T>

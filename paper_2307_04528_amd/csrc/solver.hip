@@ -584,7 +584,7 @@ mg_status chain_T(mg_handle* h, int l, const std::vector<double>& oms, bool firs
             Launch g(h, MG_K_ADJOINT, l, bytes);
             mgk::smooth_transpose<T>(view<T>(d), w.xbar, zin, zin ? w.xbar : nullptr, zout,
                                      w.fbar, T(s > 0 ? oms[s - 1] : oms[0]), T(oms[s]), acc,
-                                     h->stream);
+                                     h->opt.staged_columns, h->stream);
         }
         MG_TRY(check_launch(h, "smooth_transpose"));
         zin = zout;
