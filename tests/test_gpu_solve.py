@@ -45,6 +45,32 @@ def test_vcycle_fp64_and_transpose(sh):
     assert rel_inf(gotT, refT) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("sh", [SMALL, RAGGED, DEEP], ids=lambda s: s.name)
+def test_transposed_vcycle_staged_and_unstaged(sh, prec):
+    """The transposed V-cycle with every level's transposed sweeps staged in
+    LDS (staged_columns above every level) and with none staged: each
+    matches the oracle's transposed cycle (FP64 to 1e-12; the FP32 cycle
+    to 1e-4 in the 2-norm), and the two give the same bits (the same
+    arithmetic in the same order, only the loads staged)."""
+    a = shellgen.alpha(sh)
+    L = hierarchy(sh)
+    opt = opts_of(sh)
+    f = shellgen.rhs(sh)
+    refT = oracle.vcycle_T(L, f, opt)
+    got = {}
+    for staged in (True, False):
+        S = solver_for(sh, a, precision=prec, nu_pre=sh.nu_pre, nu_post=sh.nu_post,
+                       staged_columns=(1 << 30) if staged else 0)
+        got[staged] = n(S.vcycle(t(f), transposed=True))
+        S.close()
+    err = {k: (rel_inf(v, refT) if prec == "fp64" else rel2(v, refT)) for k, v in got.items()}
+    log(f"transposed vcycle {sh.name} {prec}: staged {err[True]:.2e} unstaged {err[False]:.2e}")
+    for e in err.values():
+        assert e < (1e-12 if prec == "fp64" else 1e-4)
+    assert np.array_equal(got[True], got[False])
+
+
 @pytest.mark.parametrize("sh", [SMALL, DEEP], ids=lambda s: s.name)
 def test_vcycle_fp32(sh):
     a = shellgen.alpha(sh)
