@@ -125,10 +125,11 @@ typedef struct {
  *                 omega. A smoothing step of one sweep (nu = 1) and the
  *                 coarsest-level sweeps always use omega.
  * staged_columns: levels with fewer columns (nlon * nlat) than this run
- *                 their sweeps with the staged kernel: eight wavefronts
- *                 load a 64-column segment into LDS in one round trip, two
- *                 solve its columns from there (default 65536; 0 = never).
- *                 Same arithmetic either way; only the speed differs.
+ *                 their sweeps, and the transposed sweeps of the adjoint
+ *                 cycle, with the staged kernels: eight wavefronts load a
+ *                 64-column segment into LDS in one round trip, two solve
+ *                 its columns from there (default 65536; 0 = never). Same
+ *                 arithmetic either way; only the speed differs.
  * stall_factor, stall_iters: stagnation guard of MG_PREC_MIXED. When
  *                 stall_iters consecutive outer iterations each leave the
  *                 residual norm above stall_factor times the previous one
