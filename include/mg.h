@@ -125,11 +125,12 @@ typedef struct {
  *                 omega. A smoothing step of one sweep (nu = 1) and the
  *                 coarsest-level sweeps always use omega.
  * staged_columns: levels with fewer columns (nlon * nlat) than this run
- *                 their sweeps, and the transposed sweeps of the adjoint
- *                 cycle, with the staged kernels: eight wavefronts load a
+ *                 their sweeps (in the forward and the transposed cycle)
+ *                 with the staged kernel: eight wavefronts load a
  *                 64-column segment into LDS in one round trip, two solve
- *                 its columns from there (default 65536; 0 = never). Same
- *                 arithmetic either way; only the speed differs.
+ *                 its columns from there (default 65536; 0 = never). The
+ *                 same operations either way, equal up to rounding; the
+ *                 speed differs.
  * stall_factor, stall_iters: stagnation guard of MG_PREC_MIXED. When
  *                 stall_iters consecutive outer iterations each leave the
  *                 residual norm above stall_factor times the previous one
@@ -177,7 +178,8 @@ enum {
     MG_K_RESTRICT,        /* fused residual + restriction                     */
     MG_K_PROLONG,         /* bilinear prolongation (add)                      */
     MG_K_COARSE,          /* coarsest-level solve                             */
-    MG_K_ADJOINT,         /* transposed-cycle kernels                         */
+    MG_K_ADJOINT,         /* unused: the transposed cycle's kernels are     */
+                          /* counted in the classes of their forward kinds  */
     MG_K_OTHER,           /* reductions, copies                               */
     MG_K_SMOOTH0,         /* first sweep of a level, from zero                */
     MG_NK

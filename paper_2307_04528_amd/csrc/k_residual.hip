@@ -55,25 +55,40 @@ static int residual_walk_range(int nI, int nJ, int nz) {
 namespace {
 using namespace dev;
 
-// y = H x (HAS_F = false) or y = f - H x, one lane per cell.
+// Rows per block of the one-lane-per-cell operator (64 columns x this many
+// rows of one layer: each wavefront one row).
+constexpr int kApplyRows = 4;
+
+// y = H x (HAS_F = false) or y = f - H x, one lane per cell, in blocks of 64
+// columns x kApplyRows rows of one layer (grid: column groups, row groups,
+// layers): a wavefront takes part of one row of one layer, so the row's
+// couplings are wave-uniform and no lane divides its index.
 template <typename T, bool HAS_F>
-__global__ __launch_bounds__(kBlock) void k_apply(LevelView<T> L, const T* __restrict__ x,
-                                                  const T* __restrict__ f, T* __restrict__ y,
-                                                  uint32_t n) {
-    const uint32_t t = global_index();
-    if (t >= n) return;
-    const uint32_t P = uint32_t(L.plane);
-    const int nJ = L.nJ, nz = L.nz;
-    const int k = int(t / P);
-    const Nb b = neighbours<false>(t - uint32_t(k) * P, L.nI, nJ);
+__global__ __launch_bounds__(64 * kApplyRows) void k_apply(LevelView<T> L,
+                                                           const T* __restrict__ x,
+                                                           const T* __restrict__ f,
+                                                           T* __restrict__ y) {
+    const int nI = L.nI, nJ = L.nJ, nz = L.nz;
+    const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
+    const int J = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kApplyRows +
+                                                 int(threadIdx.y));
+    const int k = int(blockIdx.z);
+    if (i >= nI || J >= nJ) return;
+    const size_t P = size_t(L.plane);
+    const uint32_t c = uint32_t(J) * uint32_t(nI) + uint32_t(i);
+    const uint32_t w = (i == 0) ? c + uint32_t(nI - 1) : c - 1u;
+    const uint32_t e = (i == nI - 1) ? c - uint32_t(nI - 1) : c + 1u;
+    const uint32_t sth = (J > 0) ? c - uint32_t(nI) : c;
+    const uint32_t nth = (J < nJ - 1) ? c + uint32_t(nI) : c;
+    const size_t t = size_t(k) * P + c;
     const T* xk = x + size_t(k) * P;
-    const T xc = xk[b.c];
-    const T xm = x[size_t(k > 0 ? k - 1 : 0) * P + b.c];
-    const T xp = x[size_t(k + 1 < nz ? k + 1 : k) * P + b.c];
+    const T xc = xk[c];
+    const T xm = x[size_t(k > 0 ? k - 1 : 0) * P + c];
+    const T xp = x[size_t(k + 1 < nz ? k + 1 : k) * P + c];
     const T h = L.M[t] * xc +
-                hdiff(L.Tlam[k * nJ + b.J], L.Tth[k * (nJ + 1) + b.J],
-                      L.Tth[k * (nJ + 1) + b.J + 1], xc, xk[b.w], xk[b.e], xk[b.s], xk[b.n]) +
-                L.Tr[k * nJ + b.J] * (xc - xm) + L.Tr[(k + 1) * nJ + b.J] * (xc - xp);
+                hdiff(L.Tlam[k * nJ + J], L.Tth[k * (nJ + 1) + J], L.Tth[k * (nJ + 1) + J + 1],
+                      xc, xk[w], xk[e], xk[sth], xk[nth]) +
+                L.Tr[k * nJ + J] * (xc - xm) + L.Tr[(k + 1) * nJ + J] * (xc - xp);
     y[t] = HAS_F ? f[t] - h : h;
 }
 
@@ -408,8 +423,10 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ out, T v, long 
 template <typename T>
 void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
     const long long n = L.plane * L.nz;
-    if (f) k_apply<T, true><<<blocks_for(n), kBlock, 0, s>>>(L, x, f, y, uint32_t(n));
-    else k_apply<T, false><<<blocks_for(n), kBlock, 0, s>>>(L, x, f, y, uint32_t(n));
+    const dim3 grid(unsigned((L.nI + 63) / 64), unsigned((L.nJ + kApplyRows - 1) / kApplyRows),
+                    unsigned(L.nz));
+    if (f) k_apply<T, true><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
+    else k_apply<T, false><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
 }
 
 template <typename TU, typename TE, typename TR>

@@ -23,21 +23,11 @@ namespace mgk {
 namespace {
 using namespace dev;
 
-// Rows per block of the one-lane-per-cell kernels (64 columns x this many
-// rows of one layer: each wavefront one row).
-constexpr int kRowsPerBlock = 4;
-
-// Occupancy target of the transposed sweep (waves per SIMD): caps its
-// registers.
-constexpr int kColumnWaves = 2;
 // Layers per prefetch chunk of the column kernels here.
 template <typename T>
 struct ChunkDepth {
     static constexpr int value = std::is_same<T, float>::value ? 6 : 2;
 };
-// Wavefront pairs per block of the transposed sweep (the pair's exchange is
-// a block barrier, so fewer pairs per block couple fewer columns).
-constexpr int kPairsPerBlock = 2;
 
 // Prefetch the raw loads of a chunk (FP64: the loads then stay in flight
 // while the previous chunk is solved) or combine them into the chunk's
@@ -408,141 +398,6 @@ __global__ __launch_bounds__(64 * kStageWaves) void k_smooth_staged(
     }
 }
 
-// The transposed chain kernel (k_smooth_T) on a small level, staged like
-// k_smooth_staged: eight wavefronts form xb' = (1-omega_prev) xb + omega_prev
-// sum_h T_h zin_nb (HAS_Z; else xb' = xb, and xbout is not written) and stage
-// it with the pivots and, with ACC, the old fb in LDS; one pair solves
-// H_z z = xb' (H_z is symmetric: the forward twisted solve) and writes
-// zout = z and fb = (ACC ? fb : 0) + omega z.
-template <typename T, int NZ, bool ACC>
-constexpr size_t staged_T_lds_bytes() {
-    return sizeof(T) * size_t(ACC ? 3 : 2) * NZ * 64;
-}
-
-template <typename T, int NZ, bool HAS_Z, bool ACC>
-__global__ __launch_bounds__(64 * kStageWaves) void k_smooth_T_staged(
-    LevelView<T> L, const T* xb, const T* __restrict__ zin, T* xbout, T* __restrict__ zout,
-    T* __restrict__ fb, T omega_prev, T omega, int wpr) {
-    extern __shared__ unsigned char smem_raw[];
-    T* ls = reinterpret_cast<T*>(smem_raw);   // [NZ][64] xb'_k, then y_k
-    T* lp = ls + NZ * 64;                      // [NZ][64] ip_k, then cb_k
-    T* lf = lp + NZ * 64;                      // [NZ][64] old fb (ACC)
-    __shared__ T ltr[NZ + 8];   // Tr_F of the row
-    __shared__ T xch[256];      // the pair's exchange
-    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    const int lane = int(threadIdx.x & 63u);
-    const Seg g = segment(int(blockIdx.x), L.nI, L.nJ, wpr);
-    const NbB<T> b(g);
-    const int nz = L.nz, nJ = L.nJ, J = g.J;
-    const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
-    constexpr int Q = (NZ + kStageWaves - 1) / kStageWaves;
-    const T keep = T(1) - omega_prev;
-    {
-        const int F = int(threadIdx.x);
-        const T trF = F <= nz ? L.Tr[size_t(F) * size_t(nJ) + size_t(J)] : T(0);
-        T ctl = T(0), cts = T(0), ctn = T(0);
-        if (HAS_Z && lane < Q) {
-            const int kq = clampk(wave + lane * kStageWaves, nz);
-            ctl = L.Tlam[size_t(kq) * size_t(nJ) + size_t(J)];
-            cts = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J)];
-            ctn = L.Tth[size_t(kq) * size_t(nJ + 1) + size_t(J) + 1];
-        }
-        T rb[Q], rp[Q], rf[ACC ? Q : 1], rw[HAS_Z ? Q : 1], re[HAS_Z ? Q : 1],
-            rs[HAS_Z ? Q : 1], rn[HAS_Z ? Q : 1];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int kk = clampk(wave + q * kStageWaves, nz);
-            rb[q] = ldb<T>(layer(xb, kk, Pb), b.c);
-            rp[q] = ldb<T>(layer(L.invp, kk, Pb), b.c);
-            if constexpr (ACC) rf[q] = ldb<T>(layer(fb, kk, Pb), b.c);
-            if constexpr (HAS_Z) {
-                gcptr zl = layer(zin, kk, Pb);
-                rw[q] = ldb<T>(zl, b.w);
-                re[q] = ldb<T>(zl, b.e);
-                rs[q] = ldb<T>(zl, b.s);
-                rn[q] = ldb<T>(zl, b.n);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        if (F <= nz) ltr[F] = trF;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int k = wave + q * kStageWaves;
-            if (k < nz) {
-                T sv = rb[q];
-                if constexpr (HAS_Z) {
-                    const T h = lane_value(ctl, q) * (rw[q] + re[q]) + lane_value(cts, q) * rs[q] +
-                                lane_value(ctn, q) * rn[q];
-                    sv = keep * rb[q] + omega_prev * h;
-                    // every lane has read its own xb of this layer (xbout may be xb)
-                    if (g.valid) stb<T>(layer_w(xbout, k, Pb), b.c, sv);
-                }
-                ls[k * 64 + lane] = sv;
-                lp[k * 64 + lane] = rp[q];
-                if constexpr (ACC) lf[k * 64 + lane] = rf[q];
-            }
-        }
-    }
-    __syncthreads();
-    if (wave >= 2) {
-        __syncthreads();   // the solving pair's exchange barrier
-        return;
-    }
-    const bool top = wave == 1;
-    const int m = nz >> 1;
-    T vp = T(0), sm = T(0), im = T(0);
-    if (!top) {
-#pragma unroll 4
-        for (int k = 0; k < m; ++k) {
-            const T sv = ls[k * 64 + lane], ip = lp[k * 64 + lane];
-            const T v = (sv + ltr[k] * vp) * ip;
-            ls[k * 64 + lane] = v;
-            lp[k * 64 + lane] = ltr[k + 1] * ip;
-            vp = v;
-        }
-        xch[lane] = vp;
-    } else {
-#pragma unroll 4
-        for (int k = nz - 1; k > m; --k) {
-            const T sv = ls[k * 64 + lane], ip = lp[k * 64 + lane];
-            const T v = (sv + ltr[k + 1] * vp) * ip;
-            ls[k * 64 + lane] = v;
-            lp[k * 64 + lane] = ltr[k] * ip;
-            vp = v;
-        }
-        sm = ls[m * 64 + lane];
-        im = lp[m * 64 + lane];
-        xch[64 + lane] = vp;
-        xch[128 + lane] = sm;
-        xch[192 + lane] = im;
-    }
-    __syncthreads();
-    const T zm =
-        (xch[128 + lane] + ltr[m] * xch[lane] + ltr[m + 1] * xch[64 + lane]) * xch[192 + lane];
-    auto put = [&](int k, T z) {
-        if (!g.valid) return;
-        if (zout) stb<T>(layer_w(zout, k, Pb), b.c, z);
-        T fo = omega * z;
-        if constexpr (ACC) fo += lf[k * 64 + lane];
-        stb<T>(layer_w(fb, k, Pb), b.c, fo);
-    };
-    T zv = zm;
-    if (!top) {
-#pragma unroll 4
-        for (int k = m - 1; k >= 0; --k) {
-            zv = ls[k * 64 + lane] + lp[k * 64 + lane] * zv;
-            put(k, zv);
-        }
-    } else {
-        put(m, zm);
-#pragma unroll 4
-        for (int k = m + 1; k < nz; ++k) {
-            zv = ls[k * 64 + lane] + lp[k * 64 + lane] * zv;
-            put(k, zv);
-        }
-    }
-}
-
 // The coarsest level in one launch from global memory: one block does every
 // sweep from zero, segment by segment, ping-ponging between xa and xb, with
 // a block barrier between sweeps (the global writes of a sweep are visible
@@ -670,117 +525,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_lds(LevelView<T> L, const T* 
     }
 }
 
-// Loads and stores of a per-cell array at a layer base, with the
-// non-temporal hint when NT (the policy of the forward sweep on levels of
-// fields of at least kStreamFieldBytes: arrays read or written once per
-// cell).
-template <bool NT, typename T>
-__device__ __forceinline__ T ld_pol(gcptr base, uint32_t boff) {
-    const __attribute__((address_space(1))) T* q =
-        (const __attribute__((address_space(1))) T*)(base + boff);
-    if constexpr (NT) return __builtin_nontemporal_load(q);
-    else return *q;
-}
-template <bool NT, typename T>
-__device__ __forceinline__ void st_pol(gptr base, uint32_t boff, T v) {
-    __attribute__((address_space(1))) T* q = (__attribute__((address_space(1))) T*)(base + boff);
-    if constexpr (NT) __builtin_nontemporal_store(v, q);
-    else *q = v;
-}
-
-// ---------------------------------------------------------------------------
-// Transposed sweep chain kernel:
-//   xb' = HAS_Z ? (1-omega) xb + omega sum_h T_h zin_nb : xb   (-> xbout)
-//   z = H_z^{-1} xb';  fb = (ACC ? fb : 0) + omega z;  zout = z (if set)
-// NT: the arrays read or written at the cell only with the non-temporal hint.
-template <typename T, int NZ, int D, bool HAS_Z, bool ACC, bool NT>
-__global__ __launch_bounds__(128 * kPairsPerBlock)
-__attribute__((amdgpu_waves_per_eu(kColumnWaves)))
-void k_smooth_T(LevelView<T> L, const T* xb, const T* __restrict__ zin,
-                T* xbout,  // may alias xb
-                T* __restrict__ zout, T* __restrict__ fb, T omega_prev, T omega, int wpr) {
-    constexpr int PB = kPairsPerBlock;
-    __shared__ T xch[PB][256];
-    const PairOf p = pair_of_wave();
-    const Seg g = tiled_segment(int(logical_block()), p.pair, PB, L.nI, L.nJ, wpr);
-    const NbB<T> b(g);
-    const int nJ = L.nJ, J = g.J;
-    const uint64_t Pb = uint64_t(L.plane) * sizeof(T);
-    const T keep = T(1) - omega_prev;
-    auto fetch = [&](int, int kk) {
-        StencilRaw<T> r{};
-        r.f = ld_pol<NT, T>(layer(xb, kk, Pb), b.c);
-        if constexpr (HAS_Z) {
-            gcptr zk = layer(zin, kk, Pb);
-            r.w = ldb<T>(zk, b.w);
-            r.e = ldb<T>(zk, b.e);
-            r.s = ldb<T>(zk, b.s);
-            r.n = ldb<T>(zk, b.n);
-        }
-        return r;
-    };
-    auto comb = [&](int, int kk, const StencilRaw<T>& r) -> T {
-        if constexpr (HAS_Z) {
-            const T h = tab(L.Tlam, kk * nJ + J) * (r.w + r.e) +
-                        tab(L.Tth, kk * (nJ + 1) + J) * r.s +
-                        tab(L.Tth, kk * (nJ + 1) + J + 1) * r.n;
-            return keep * r.f + omega_prev * h;
-        }
-        return r.f;
-    };
-    auto inv = [&](int kk) -> T { return ld_pol<NT, T>(layer(L.invp, kk, Pb), b.c); };
-    auto cpl = [&](int F) -> T { return tab(L.Tr, F * nJ + J); };
-    auto fsink = [&](int, int kk, T s) {
-        if constexpr (HAS_Z) {
-            if (g.valid) st_pol<NT, T>(layer_w(xbout, kk, Pb), b.c, s);
-        }
-    };
-    auto bload = [&](int kk) -> T { return ld_pol<NT, T>(layer(fb, kk, Pb), b.c); };
-    auto sink = [&](int, int kk, T z, T e) {
-        T fo = omega * z;
-        if constexpr (ACC) fo += e;
-        if (g.valid) {
-            if (zout) st_pol<NT, T>(layer_w(zout, kk, Pb), b.c, z);
-            st_pol<NT, T>(layer_w(fb, kk, Pb), b.c, fo);
-        }
-    };
-    twisted_column<T, NZ, D, ACC>(L.nz, p.top, xch[p.pair], fetch, comb, inv, cpl, fsink, bload,
-                                  sink);
-}
-
-// xb = (1-omega) xb + omega sum_h T_h z_nb, one lane per cell. Blocks of
-// 64 columns x kRowsPerBlock rows of one layer (grid: column groups, row
-// groups, layers): a wavefront takes part of one row of one layer, so the
-// row's couplings are wave-uniform and no lane divides its index.
-template <typename T>
-__global__ __launch_bounds__(64 * kRowsPerBlock) void k_adjoint_stencil(LevelView<T> L,
-                                                                        const T* __restrict__ z,
-                                                                        T* __restrict__ xb,
-                                                                        T omega) {
-    const int nI = L.nI, nJ = L.nJ;
-    const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
-    const int J = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
-                                                 int(threadIdx.y));
-    const int k = int(blockIdx.z);
-    if (i >= nI || J >= nJ) return;
-    const uint32_t col = uint32_t(J) * uint32_t(nI) + uint32_t(i);
-    const uint32_t w = (i == 0) ? col + uint32_t(nI - 1) : col - 1u;
-    const uint32_t e = (i == nI - 1) ? col - uint32_t(nI - 1) : col + 1u;
-    const uint32_t sn = (J > 0) ? col - uint32_t(nI) : col;
-    const uint32_t nn = (J < nJ - 1) ? col + uint32_t(nI) : col;
-    const T* zk = z + size_t(k) * size_t(L.plane);
-    const size_t t = size_t(k) * size_t(L.plane) + col;
-    const T h = L.Tlam[k * nJ + J] * (zk[w] + zk[e]) + L.Tth[k * (nJ + 1) + J] * zk[sn] +
-                L.Tth[k * (nJ + 1) + J + 1] * zk[nn];
-    xb[t] = (T(1) - omega) * xb[t] + omega * h;
-}
-
-// Blocks of PB wavefront pairs (row tiles of PB rows) covering every segment.
-template <typename T>
-inline int pair_blocks(const int nJ, const int wpr) {
-    return tiled_blocks(nJ, wpr, kPairsPerBlock);
-}
-
 }  // namespace
 
 constexpr size_t kMaxLds = 160 * 1024;
@@ -863,87 +607,6 @@ int coarse_solve(const LevelView<T>& L, const T* f, T* xa, T* xb, T omega, int s
     return (sweeps & 1) ? 0 : 1;
 }
 
-// The staged transposed chain kernel on a small level; false where the level
-// is not small or the staging buffers do not fit in LDS.
-template <typename T>
-bool launch_staged_T(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
-                     T* fb, T omega_prev, T omega, bool accumulate, long long staged_columns,
-                     hipStream_t s) {
-    if (L.plane >= staged_columns) return false;
-    const int wpr = segments_per_row(L.nI);
-    const int nb = L.nJ * wpr;
-    bool launched = false;
-    with_nz(L.nz, [&](auto nzc) {
-        constexpr int NZ = decltype(nzc)::value;
-        auto go = [&](auto hz, auto ac) {
-            constexpr bool HZ = decltype(hz)::value, AC = decltype(ac)::value;
-            constexpr size_t lds = staged_T_lds_bytes<T, NZ, AC>();
-            if constexpr (lds + sizeof(T) * (NZ + 8 + 256) <= kMaxLds) {
-                const void* fn = reinterpret_cast<const void*>(&k_smooth_T_staged<T, NZ, HZ, AC>);
-                if (lds > 64 * 1024 &&
-                    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(lds)) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return;
-                }
-                k_smooth_T_staged<T, NZ, HZ, AC><<<nb, 64 * kStageWaves, lds, s>>>(
-                    L, xb, zin, xbout, zout, fb, omega_prev, omega, wpr);
-                launched = true;
-            }
-        };
-        using Tt = std::true_type;
-        using Ff = std::false_type;
-        if (zin) {
-            if (accumulate) go(Tt{}, Tt{}); else go(Tt{}, Ff{});
-        } else {
-            if (accumulate) go(Ff{}, Tt{}); else go(Ff{}, Ff{});
-        }
-    });
-    return launched;
-}
-
-template <typename T>
-void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout, T* zout,
-                      T* fb, T omega_prev, T omega, bool accumulate, long long staged_columns,
-                      hipStream_t s) {
-    if (launch_staged_T<T>(L, xb, zin, xbout, zout, fb, omega_prev, omega, accumulate,
-                           staged_columns, s))
-        return;
-    const int wpr = segments_per_row(L.nI);
-    const int nb = pair_blocks<T>(L.nJ, wpr);
-    constexpr int threads = 128 * kPairsPerBlock;
-    const bool stream = L.plane * L.nz * (long long)sizeof(T) >= kStreamFieldBytes;
-    with_nz(L.nz, [&](auto nzc) {
-        constexpr int NZ = decltype(nzc)::value;
-        constexpr int D = ChunkDepth<T>::value;
-        auto go = [&](auto hz, auto ac, auto nt) {
-            k_smooth_T<T, NZ, D, decltype(hz)::value, decltype(ac)::value, decltype(nt)::value>
-                <<<nb, threads, 0, s>>>(L, xb, zin, xbout, zout, fb, omega_prev, omega, wpr);
-        };
-        auto pick = [&](auto hz, auto ac) {
-            // the hinted variant for the 70-layer bucket only
-            if constexpr (NZ == 72) {
-                if (stream) return go(hz, ac, std::true_type{});
-            }
-            go(hz, ac, std::false_type{});
-        };
-        using Tt = std::true_type;
-        using Ff = std::false_type;
-        if (zin) {
-            if (accumulate) pick(Tt{}, Tt{}); else pick(Tt{}, Ff{});
-        } else {
-            if (accumulate) pick(Ff{}, Tt{}); else pick(Ff{}, Ff{});
-        }
-    });
-}
-
-template <typename T>
-void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s) {
-    const dim3 grid(unsigned((L.nI + 63) / 64), unsigned((L.nJ + kRowsPerBlock - 1) / kRowsPerBlock),
-                    unsigned(L.nz));
-    k_adjoint_stencil<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(L, z, xb, omega);
-}
-
 bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int sweeps,
                   size_t max_lds, hipStream_t s) {
     const long long n = L.plane * L.nz;
@@ -955,10 +618,7 @@ bool coarse_basis(const LevelView<double>& L, double* Ct, double omega, int swee
     template void smooth<T>(const LevelView<T>&, const T*, const T*, T*, T, long long,      \
                             hipStream_t);                                                   \
     template int coarse_solve<T>(const LevelView<T>&, const T*, T*, T*, T, int, size_t,       \
-                                 hipStream_t);                                              \
-    template void smooth_transpose<T>(const LevelView<T>&, const T*, const T*, T*, T*, T*, \
-                                      T, T, bool, long long, hipStream_t);                  \
-    template void adjoint_stencil<T>(const LevelView<T>&, const T*, T*, T, hipStream_t);
+                                 hipStream_t);
 MG_INST(float)
 MG_INST(double)
 #undef MG_INST

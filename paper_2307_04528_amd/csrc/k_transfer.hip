@@ -355,36 +355,23 @@ __global__ __launch_bounds__(64 * kRowsPerBlock) void k_prolong_T(LevelView<T> F
     xc[t] = acc;
 }
 
-// fb += y, xb -= H y with y = R^T fcb (every child takes its coarse value),
-// one lane per fine cell, in blocks of 64 columns x kRowsPerBlock rows of one
-// layer (the row's couplings and coarse rows wave-uniform).
+// x += R^T xc (every child takes its coarse value), one lane per fine cell,
+// in blocks of 64 columns x kRowsPerBlock rows of one layer (the row's
+// coarse row wave-uniform).
 template <typename T>
-__global__ __launch_bounds__(64 * kRowsPerBlock) void k_inject_residual_adj(
-    LevelView<T> F, TransferView<T> X, const T* __restrict__ fcb, T* __restrict__ xb,
-    T* __restrict__ fb) {
-    const int nI = F.nI, nJ = F.nJ, nz = F.nz, nIc = X.nIc;
+__global__ __launch_bounds__(64 * kRowsPerBlock) void k_inject_add(LevelView<T> F,
+                                                                   TransferView<T> X,
+                                                                   const T* __restrict__ xc,
+                                                                   T* __restrict__ x) {
+    const int nI = F.nI, nJ = F.nJ, nIc = X.nIc;
     const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
     const int j = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
                                                  int(threadIdx.y));
     const int k = int(blockIdx.z);
     if (i >= nI || j >= nJ) return;
     const size_t t = size_t(k) * size_t(F.plane) + size_t(j) * size_t(nI) + size_t(i);
-    const size_t Pc = size_t(nIc) * X.nJc;
-    const int iw = (i == 0) ? nI - 1 : i - 1, ie = (i == nI - 1) ? 0 : i + 1;
-    const int oc = X.crow_of[j] * nIc;
-    const int cc = oc + (i >> 1), cw = oc + (iw >> 1), ce = oc + (ie >> 1);
-    const int cs = (j > 0) ? X.crow_of[j - 1] * nIc + (i >> 1) : cc;
-    const int cn = (j < nJ - 1) ? X.crow_of[j + 1] * nIc + (i >> 1) : cc;
-    const T* lay = fcb + size_t(k) * Pc;
-    const T yc = lay[cc];
-    const T ym = fcb[size_t(k > 0 ? k - 1 : 0) * Pc + cc];
-    const T yp = fcb[size_t(k + 1 < nz ? k + 1 : k) * Pc + cc];
-    const T h = F.M[t] * yc +
-                hdiff(F.Tlam[k * nJ + j], F.Tth[k * (nJ + 1) + j], F.Tth[k * (nJ + 1) + j + 1],
-                      yc, lay[cw], lay[ce], lay[cs], lay[cn]) +
-                F.Tr[k * nJ + j] * (yc - ym) + F.Tr[(k + 1) * nJ + j] * (yc - yp);
-    fb[t] += yc;
-    xb[t] -= h;
+    const size_t tc = (size_t(k) * X.nJc + size_t(X.crow_of[j])) * size_t(nIc) + size_t(i >> 1);
+    x[t] += xc[tc];
 }
 
 }  // namespace
@@ -449,11 +436,11 @@ void prolong_transpose(const LevelView<T>& F, const TransferView<T>& X, const T*
 }
 
 template <typename T>
-void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X, const T* fcb,
-                             T* xb, T* fb, hipStream_t s) {
+void inject_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T* x,
+                hipStream_t s) {
     const dim3 grid(unsigned((F.nI + 63) / 64), unsigned((F.nJ + kRowsPerBlock - 1) / kRowsPerBlock),
                     unsigned(F.nz));
-    k_inject_residual_adj<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, fcb, xb, fb);
+    k_inject_add<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, xc, x);
 }
 
 #define MG_INST(T)                                                                       \
@@ -463,8 +450,8 @@ void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X, co
                                  T*, hipStream_t);                                        \
     template void prolong_transpose<T>(const LevelView<T>&, const TransferView<T>&,      \
                                        const T*, T*, hipStream_t);                        \
-    template void inject_residual_adjoint<T>(const LevelView<T>&, const TransferView<T>&, \
-                                             const T*, T*, T*, hipStream_t);
+    template void inject_add<T>(const LevelView<T>&, const TransferView<T>&, const T*, T*, \
+                                hipStream_t);
 MG_INST(float)
 MG_INST(double)
 #undef MG_INST

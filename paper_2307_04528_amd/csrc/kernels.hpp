@@ -125,26 +125,10 @@ template <typename T>
 void prolong_transpose(const LevelView<T>& F, const TransferView<T>& X, const T* x,
                        T* xc, hipStream_t s);
 
-// Adjoint of the residual restriction: y = R^T fcb (injection);
-// fb += y; xb -= H y.
+// x += R^T xc (every child cell takes its coarse parent's value).
 template <typename T>
-void inject_residual_adjoint(const LevelView<T>& F, const TransferView<T>& X,
-                             const T* fcb, T* xb, T* fb, hipStream_t s);
-
-// One kernel of the transposed smoother chain (it completes the transposed
-// sweep before it, of factor omega_prev, and starts the next, of factor omega):
-//   xb' = zin ? (1-omega_prev) xb + omega_prev sum_h T_h zin_nb : xb
-//         (-> xbout if set)
-//   z   = H_z^{-1} xb';  fb = (accumulate ? fb : 0) + omega z;  zout = z if set.
-// Levels of fewer than staged_columns columns use the staged kernel.
-template <typename T>
-void smooth_transpose(const LevelView<T>& L, const T* xb, const T* zin, T* xbout,
-                      T* zout, T* fb, T omega_prev, T omega, bool accumulate,
-                      long long staged_columns, hipStream_t s);
-
-// xb = (1-omega) xb + omega sum_h T_h z_nb (in place on xb).
-template <typename T>
-void adjoint_stencil(const LevelView<T>& L, const T* z, T* xb, T omega, hipStream_t s);
+void inject_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T* x,
+                hipStream_t s);
 
 // Refinement step on the finest level, in the iterate's precision TU (FP64;
 // FP32 in the pure single-precision solve):

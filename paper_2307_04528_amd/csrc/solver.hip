@@ -10,7 +10,13 @@
 //   x = omega H_z^{-1} f; (nu_pre - 1) more sweeps;
 //   f_{l+1} = R (f - H x); x_{l+1} = V_{l+1}(f_{l+1}); x += P x_{l+1};
 //   nu_post sweeps; the coarsest level does coarse_sweeps sweeps from zero.
-// The transposed V-cycle reverses these steps (adjoint solve).
+// The transposed V-cycle (adjoint solve) is the transpose of that map f -> x.
+// H and every H_z are symmetric, so the transpose of a chain of sweeps from
+// zero is the chain of the same sweeps in reverse order from zero, and the
+// transposed cycle has the forward cycle's shape: nu_post sweeps with the
+// post-smoothing factors reversed; f_{l+1} = P^T (f - H x); the transposed
+// coarse cycle; x += R^T x_{l+1}; nu_pre sweeps with the pre-smoothing
+// factors reversed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,10 +43,6 @@ struct Work {
     T* f = nullptr;     // right-hand side of the level
     T* xa = nullptr;    // iterate (ping)
     T* xb = nullptr;    // iterate (pong)
-    T* xbar = nullptr;  // adjoint: transposed iterate
-    T* za = nullptr;    // adjoint: column solves (ping)
-    T* zb = nullptr;    // adjoint: column solves (pong)
-    T* fbar = nullptr;  // adjoint: output of the transposed cycle
 };
 
 struct DevLevel {
@@ -260,7 +262,7 @@ mg_status ensure_work(mg_handle* h) {
     if (have) return MG_OK;
     for (auto& d : h->lv) {
         Work<T>& w = work<T>(d);
-        for (T** p : {&w.f, &w.xa, &w.xb, &w.xbar, &w.za, &w.zb, &w.fbar})
+        for (T** p : {&w.f, &w.xa, &w.xb})
             MG_TRY(dalloc(h, p, d.n));
     }
     have = true;
@@ -565,89 +567,92 @@ mg_status capture_graphs(mg_handle* h) {
     return capture_coarse<double>(h);
 }
 
-// Transposed smoother chain starting from xbar (no pending column solve):
-// the transposed sweeps of factors oms[0], oms[1], ... in that order. Leaves
-// the last column solve in *zlast (its stencil pending) and accumulates fbar.
-// first_sets_fbar: the first kernel writes fbar instead of adding to it.
 template <typename T>
-mg_status chain_T(mg_handle* h, int l, const std::vector<double>& oms, bool first_sets_fbar,
-                  T** zlast) {
-    DevLevel& d = h->lv[l];
-    Work<T>& w = work<T>(d);
-    T* zin = nullptr;
-    T* zout = w.za;
-    const int sweeps = int(oms.size());
-    for (int s = 0; s < sweeps; ++s) {
-        const bool acc = !(first_sets_fbar && s == 0);
-        const double bytes = double(d.n) * sizeof(T) * (zin ? 6 : 4);
-        {
-            Launch g(h, MG_K_ADJOINT, l, bytes);
-            mgk::smooth_transpose<T>(view<T>(d), w.xbar, zin, zin ? w.xbar : nullptr, zout,
-                                     w.fbar, T(s > 0 ? oms[s - 1] : oms[0]), T(oms[s]), acc,
-                                     h->opt.staged_columns, h->stream);
-        }
-        MG_TRY(check_launch(h, "smooth_transpose"));
-        zin = zout;
-        zout = (zout == w.za) ? w.zb : w.za;
+mg_status op_restrict_T(mg_handle* h, int l, const T* f, const T* x, T* r, T* fc) {
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    {
+        Launch g(h, MG_K_RESTRICT, l, double(d.n) * sizeof(T) * 4);
+        mgk::apply<T>(view<T>(d), x, f, r, h->stream);
     }
-    *zlast = zin;
-    return MG_OK;
+    MG_TRY(check_launch(h, "apply"));
+    {
+        Launch g(h, MG_K_RESTRICT, l, double(d.n) * sizeof(T) + double(c.n) * sizeof(T));
+        mgk::prolong_transpose<T>(view<T>(d), xview<T>(d, c), r, fc, h->stream);
+    }
+    return check_launch(h, "prolong_transpose");
 }
 
-// Transposed V-cycle on level l applied to g (in work.xbar on entry); the
-// result is left in work.fbar.
 template <typename T>
-mg_status vcycle_T(mg_handle* h, int l) {
+mg_status op_inject(mg_handle* h, int l, const T* xc, T* x) {
+    DevLevel &d = h->lv[l], &c = h->lv[l + 1];
+    {
+        Launch g(h, MG_K_PROLONG, l, double(d.n) * sizeof(T) * 2 + double(c.n) * sizeof(T));
+        mgk::inject_add<T>(view<T>(d), xview<T>(d, c), xc, x, h->stream);
+    }
+    return check_launch(h, "inject_add");
+}
+
+// The transposed V-cycle from zero on level l (the transpose of the map
+// f -> vcycle(f)); returns the buffer holding the result. A transposed sweep
+// sends (xbar, fbar) to (xbar - omega H H_z^{-1} xbar, fbar + omega H_z^{-1}
+// xbar): the step of a sweep on the right-hand side xbar whose iterate is
+// fbar and whose residual is xbar. So the transposed steps, taken in reverse
+// order, are forward sweeps from zero (factors reversed), the transposes of
+// the transfers (P^T restricts the residual, R^T injects the correction) and
+// the transposed coarse solve.
+template <typename T>
+mg_status vcycle_adj(mg_handle* h, int l, const T* f, T** result) {
     DevLevel& d = h->lv[l];
     Work<T>& w = work<T>(d);
     const int last = int(h->lv.size()) - 1;
-    const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
-    T* z = nullptr;
+    T* cur = w.xa;
+    T* nxt = w.xb;
     if (l == last) {
         if (h->dense.valid) {
-            // fbar = C^T xbar
             {
                 Launch g(h, MG_K_COARSE, l, double(d.n) * (d.n + 2) * sizeof(T));
-                mgk::dense_matvec<T>(dense_C<T>(h, true), d.n, w.xbar, w.fbar, h->stream);
+                mgk::dense_matvec<T>(dense_C<T>(h, true), d.n, f, cur, h->stream);
             }
-            return check_launch(h, "dense transposed coarse solve");
+            MG_TRY(check_launch(h, "dense transposed coarse solve"));
+            *result = cur;
+            return MG_OK;
         }
-        // (coarse_sweeps - 1) transposed sweeps, then the transposed first
-        // sweep: fbar += omega H_z^{-1} xbar, all as one chain
-        return chain_T<T>(h, l, std::vector<double>(h->opt.coarse_sweeps, h->opt.omega), true,
-                          &z);
+        // sweeps from zero with one factor: a symmetric map, its own transpose
+        return vcycle<T>(h, l, f, result);
     }
-    // post-sweeps, last first
+    const int nu1 = h->opt.nu_pre, nu2 = h->opt.nu_post;
+    Work<T>& wc = work<T>(h->lv[l + 1]);
     if (nu2 > 0) {
-        std::vector<double> oms;
-        for (int s = nu2 - 1; s >= 0; --s) oms.push_back(mgs::sweep_omega(h->opt, nu2, s));
-        MG_TRY(chain_T<T>(h, l, oms, true, &z));
-        {
-            Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) * 3);
-            mgk::adjoint_stencil<T>(view<T>(d), z, w.xbar, T(oms.back()), h->stream);
+        MG_TRY(op_smooth<T>(h, l, f, nullptr, cur, MG_K_SMOOTH0,
+                            mgs::sweep_omega(h->opt, nu2, nu2 - 1)));
+        for (int s = nu2 - 2; s >= 0; --s) {
+            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH, mgs::sweep_omega(h->opt, nu2, s)));
+            std::swap(cur, nxt);
         }
-        MG_TRY(check_launch(h, "adjoint_stencil"));
+        MG_TRY(op_restrict_T<T>(h, l, f, cur, nxt, wc.f));
     } else {
-        mgk::fill<T>(w.fbar, T(0), d.n, h->stream);
+        // no sweeps: the iterate is zero and its residual is f
+        {
+            DevLevel& c = h->lv[l + 1];
+            Launch g(h, MG_K_RESTRICT, l, double(d.n) * sizeof(T) + double(c.n) * sizeof(T));
+            mgk::prolong_transpose<T>(view<T>(d), xview<T>(d, c), f, wc.f, h->stream);
+        }
+        MG_TRY(check_launch(h, "prolong_transpose"));
+        mgk::fill<T>(cur, T(0), d.n, h->stream);
+        MG_TRY(check_launch(h, "fill"));
     }
-    DevLevel& c = h->lv[l + 1];
-    Work<T>& wc = work<T>(c);
+    T* xc = nullptr;
+    MG_TRY(vcycle_adj<T>(h, l + 1, wc.f, &xc));
+    MG_TRY(op_inject<T>(h, l, xc, cur));
     {
-        Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) + double(c.n) * sizeof(T));
-        mgk::prolong_transpose<T>(view<T>(d), xview<T>(d, c), w.xbar, wc.xbar, h->stream);
+        SweepGroup g(h, l, nu1, double(nu1) * double(d.n) * sizeof(T) * 4);
+        for (int s = nu1 - 1; s >= 0; --s) {
+            MG_TRY(op_smooth<T>(h, l, f, cur, nxt, MG_K_SMOOTH, mgs::sweep_omega(h->opt, nu1, s)));
+            std::swap(cur, nxt);
+        }
     }
-    MG_TRY(check_launch(h, "prolong_transpose"));
-    MG_TRY(vcycle_T<T>(h, l + 1));
-    {
-        Launch g(h, MG_K_ADJOINT, l, double(d.n) * sizeof(T) * 5 + double(c.n) * sizeof(T));
-        mgk::inject_residual_adjoint<T>(view<T>(d), xview<T>(d, c), wc.fbar, w.xbar, w.fbar,
-                                        h->stream);
-    }
-    MG_TRY(check_launch(h, "inject_residual_adjoint"));
-    // the transposed pre-sweeps, last first, ending with the first sweep
-    std::vector<double> oms;
-    for (int s = nu1 - 1; s >= 0; --s) oms.push_back(mgs::sweep_omega(h->opt, nu1, s));
-    return chain_T<T>(h, l, oms, false, &z);
+    *result = cur;
+    return MG_OK;
 }
 
 // Copy the reduced scalar to the host (asynchronously; the copy's completion
@@ -757,21 +762,17 @@ mg_status outer(mg_handle* h, const double* b, double* u, double tol, mg_stats* 
         ucur = zero ? nullptr : h->u32a;
     }
     // r0 = b - H u0 (the fine-level right-hand side of the first V-cycle)
-    T* r = transposed ? w.xbar : w.f;
+    T* r = w.f;
     double rn = 0;
     // (||b|| in the same pass)
     MG_TRY((refine_step<T, U>(h, bU, ucur, nullptr, nullptr, r, true)));
     // enqueue one V-cycle on r; its correction e is what the next step adds
     auto cycle = [&](const T** e) -> mg_status {
         Phase ph(h, 0);
-        if (!transposed) {
-            T* x = nullptr;
-            MG_TRY(vcycle<T>(h, 0, w.f, &x));
-            *e = x;
-        } else {
-            MG_TRY(vcycle_T<T>(h, 0));
-            *e = w.fbar;
-        }
+        T* x = nullptr;
+        if (!transposed) MG_TRY(vcycle<T>(h, 0, w.f, &x));
+        else MG_TRY(vcycle_adj<T>(h, 0, w.f, &x));
+        *e = x;
         return MG_OK;
     };
     // The first cycle is almost always needed: enqueue it before the wait
@@ -1084,16 +1085,11 @@ mg_status one_vcycle(mg_handle* h, const double* f, double* x, bool transposed) 
     MG_TRY(ensure_work<T>(h));
     DevLevel& d = h->lv[0];
     Work<T>& w = work<T>(d);
-    if (!transposed) {
-        to_level<T>(h, f, w.f, d.n);
-        T* out = nullptr;
-        MG_TRY(vcycle<T>(h, 0, w.f, &out));
-        from_level<T>(h, out, x, d.n);
-    } else {
-        to_level<T>(h, f, w.xbar, d.n);
-        MG_TRY(vcycle_T<T>(h, 0));
-        from_level<T>(h, w.fbar, x, d.n);
-    }
+    to_level<T>(h, f, w.f, d.n);
+    T* out = nullptr;
+    if (!transposed) MG_TRY(vcycle<T>(h, 0, w.f, &out));
+    else MG_TRY(vcycle_adj<T>(h, 0, w.f, &out));
+    from_level<T>(h, out, x, d.n);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return check_launch(h, "vcycle");
 }

@@ -48,11 +48,10 @@ def test_vcycle_fp64_and_transpose(sh):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("sh", [SMALL, RAGGED, DEEP], ids=lambda s: s.name)
 def test_transposed_vcycle_staged_and_unstaged(sh, prec):
-    """The transposed V-cycle with every level's transposed sweeps staged in
-    LDS (staged_columns above every level) and with none staged: each
+    """The transposed V-cycle with every level's sweeps staged in LDS
+    (staged_columns above every level) and with none staged: each
     matches the oracle's transposed cycle (FP64 to 1e-12; the FP32 cycle
-    to 1e-4 in the 2-norm), and the two give the same bits (the same
-    arithmetic in the same order, only the loads staged)."""
+    to 1e-4 in the 2-norm), and the two agree to rounding."""
     a = shellgen.alpha(sh)
     L = hierarchy(sh)
     opt = opts_of(sh)
@@ -68,7 +67,10 @@ def test_transposed_vcycle_staged_and_unstaged(sh, prec):
     log(f"transposed vcycle {sh.name} {prec}: staged {err[True]:.2e} unstaged {err[False]:.2e}")
     for e in err.values():
         assert e < (1e-12 if prec == "fp64" else 1e-4)
-    assert np.array_equal(got[True], got[False])
+    # the two sweep kernels round differently (the pair kernel multiplies
+    # precomputed step records): equal to rounding, not bit for bit
+    d = rel_inf(got[True], got[False]) if prec == "fp64" else rel2(got[True], got[False])
+    assert d < (1e-13 if prec == "fp64" else 1e-4)
 
 
 @pytest.mark.parametrize("sh", [SMALL, DEEP], ids=lambda s: s.name)
@@ -258,10 +260,13 @@ def test_autograd_finite_differences_small():
     del torch
 
 
-@pytest.mark.parametrize("nu", [(2, 2), (2, 1)])
+@pytest.mark.parametrize("nu", [(2, 2), (2, 1), (1, 3), (2, 4), (2, 0)])
 def test_vcycle_chebyshev_smoothing(nu):
     """Per-sweep damping factors from the Chebyshev nodes of [1/3, 2]: the
-    forward and transposed V-cycles against the oracle's, and a solve."""
+    forward and transposed V-cycles against the oracle's (asymmetric cycles,
+    whose transposes swap the two smoothing steps, and a cycle without
+    post-smoothing, whose transpose starts from a zero iterate), and a
+    solve."""
     sh = DEEP
     a, f = shellgen.alpha(sh), shellgen.rhs(sh)
     S = solver_for(sh, a, precision="fp64", nu_pre=nu[0], nu_post=nu[1],

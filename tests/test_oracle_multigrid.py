@@ -203,6 +203,43 @@ def test_chebyshev_sweep_factors_closed_form():
     assert sweep_omegas(Options(omega=0.7, smooth_lo=0.0), 3) == [0.7, 0.7, 0.7]
 
 
+def _transposed_as_forward(L, g, opt, l=0):
+    """The transposed V-cycle in the shape of a forward one: with H and H_z
+    symmetric a transposed sweep is a forward sweep on the right-hand side
+    xbar (its iterate fbar, its residual xbar), so the reversed chain of
+    transposed sweeps is a chain of forward sweeps from zero with the
+    factors reversed; the transfers enter transposed (P^T restricts the
+    residual, R^T = injection prolongates)."""
+    from oracle.multigrid import coarse_solve, sweep, sweep_from_zero, sweep_omegas
+    lev = L[l]
+    if l == len(L) - 1:
+        return coarse_solve(lev, g, opt)
+    pre, post = sweep_omegas(opt, opt.nu_pre), sweep_omegas(opt, opt.nu_post)
+    x = np.zeros_like(g)
+    for i, w in enumerate(reversed(post)):
+        x = sweep_from_zero(lev, g, w) if i == 0 else sweep(lev, x, g, w)
+    xc = _transposed_as_forward(L, prolong_T(lev, L[l + 1], g - apply(lev, x)), opt, l + 1)
+    x = x + inject(lev, L[l + 1], xc)
+    for w in reversed(pre):
+        x = sweep(lev, x, g, w)
+    return x
+
+
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (2, 1), (1, 3), (2, 4), (2, 0)])
+@pytest.mark.parametrize("interval", [(1 / 3, 2.0), (0.0, 2.0)], ids=["chebyshev", "constant"])
+def test_transposed_cycle_is_a_forward_cycle(nu, interval):
+    """The step-by-step transposed V-cycle equals the forward-shaped one
+    (swapped smoothing steps with reversed factors, transposed transfers),
+    the form the GPU path computes, on a ragged hierarchy."""
+    sh, L = _setup(36, 18, 6, q=1.15)
+    opt = Options(nu_pre=nu[0], nu_post=nu[1], coarse_sweeps=5, smooth_lo=interval[0],
+                  smooth_hi=interval[1])
+    g = np.random.default_rng(23).standard_normal(sh.shape)
+    ref = vcycle_T(L, g, opt)
+    got = _transposed_as_forward(L, g, opt)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("nu", [(2, 2), (2, 1)])
 def test_chebyshev_vcycle_transpose_and_convergence(nu):
     sh, L = _setup(32, 16, 5, q=1.2)
