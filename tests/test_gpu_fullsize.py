@@ -8,7 +8,9 @@ entry points and launch configuration that bench.py times.
     without the staged kernel; the fused residual-restriction of the two
     largest levels; the mixed solve to relative residual 1e-8,
     with ||b - H u|| / ||b|| of the returned u recomputed by the oracle on
-    the host.
+    the host; one FP32 and one FP64 transposed V-cycle against the oracle's
+    over the whole field, and the adjoint solve to 1e-8 with its residual
+    recomputed on the host.
   * shell2560x1920x70 (344M cells): the mixed solve to 1e-8, its residual
     recomputed by the oracle on the host (a whole oracle V-cycle at this size
     is too slow for a test; the per-cycle parity is covered above).
@@ -50,6 +52,43 @@ def test_bench_vcycle_full_field(prec):
     log(f"full-size vcycle {prec}: {err:.2e}")
     assert err < (1e-12 if prec == "fp64" else 1e-4)
     S.close()
+
+
+@functools.lru_cache(maxsize=1)
+def bench_vcycle_T_ref():
+    log(f"[oracle] one transposed V({BENCH.nu_pre},{BENCH.nu_post}) cycle on shell1024x768x70")
+    return oracle.vcycle_T(bench_levels(), shellgen.weights(BENCH), opts_of(BENCH))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bench_transposed_vcycle_full_field(prec):
+    """The transposed V-cycle (the adjoint solve's cycle) on the benchmark
+    workload against the oracle's step-by-step transposed cycle, element
+    by element over the whole field."""
+    S = solver_for(BENCH, shellgen.alpha(BENCH), precision=prec, nu_pre=BENCH.nu_pre,
+                   nu_post=BENCH.nu_post)
+    got = n(S.vcycle(t(shellgen.weights(BENCH)), transposed=True))
+    S.close()
+    ref = bench_vcycle_T_ref()
+    err = rel_inf(got, ref) if prec == "fp64" else rel2(got, ref)
+    log(f"full-size transposed vcycle {prec}: {err:.2e}")
+    assert err < (1e-12 if prec == "fp64" else 1e-4)
+
+
+def test_bench_adjoint_solve_residual_checked_on_host():
+    """The adjoint solve that bench.py times: H^T lambda = w to relative
+    residual 1e-8, with ||w - H^T lambda|| / ||w|| of the returned lambda
+    recomputed by the oracle on the host (H is symmetric)."""
+    a, w = shellgen.alpha(BENCH), shellgen.weights(BENCH)
+    S = solver_for(BENCH, a, precision="mixed", nu_pre=BENCH.nu_pre, nu_post=BENCH.nu_post)
+    lam, st = S.solve_adjoint(t(w), tol=1e-8)
+    lam = n(lam)
+    S.close()
+    fine = oracle.build_hierarchy(BENCH, a, levels=1)[0]
+    relres = float(np.linalg.norm((w - oracle.apply(fine, lam)).ravel()) / np.linalg.norm(w.ravel()))
+    log(f"adjoint solve: {st.iters} iterations, relres {st.relres:.3e}, on the host {relres:.3e}")
+    assert relres <= 1e-8
+    assert relres == pytest.approx(st.relres, rel=1e-3)
 
 
 def test_bench_finest_sweeps_full_field():
