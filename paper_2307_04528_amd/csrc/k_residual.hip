@@ -55,24 +55,28 @@ static int residual_walk_range(int nI, int nJ, int nz) {
 namespace {
 using namespace dev;
 
-// Rows per block of the one-lane-per-cell operator (64 columns x this many
-// rows of one layer: each wavefront one row).
+// Rows per block of the operator kernel (64 columns x this many rows: each
+// wavefront one row) and layers per lane (a lane walks a chunk of layers of
+// its column: the chunk's loads are in flight together, and the vertical
+// neighbours come from the layers it already loaded).
 constexpr int kApplyRows = 4;
+constexpr int kApplyLayers = 4;
 
-// y = H x (HAS_F = false) or y = f - H x, one lane per cell, in blocks of 64
-// columns x kApplyRows rows of one layer (grid: column groups, row groups,
-// layers): a wavefront takes part of one row of one layer, so the row's
-// couplings are wave-uniform and no lane divides its index.
+// y = H x (HAS_F = false) or y = f - H x, one lane per column and chunk of
+// kApplyLayers layers, in blocks of 64 columns x kApplyRows rows (grid:
+// column groups, row groups, layer chunks): a wavefront takes part of one
+// row, so the row's couplings are wave-uniform and no lane divides its index.
 template <typename T, bool HAS_F>
 __global__ __launch_bounds__(64 * kApplyRows) void k_apply(LevelView<T> L,
                                                            const T* __restrict__ x,
                                                            const T* __restrict__ f,
                                                            T* __restrict__ y) {
+    constexpr int NL = kApplyLayers;
     const int nI = L.nI, nJ = L.nJ, nz = L.nz;
     const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
     const int J = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kApplyRows +
                                                  int(threadIdx.y));
-    const int k = int(blockIdx.z);
+    const int k0 = int(blockIdx.z) * NL;
     if (i >= nI || J >= nJ) return;
     const size_t P = size_t(L.plane);
     const uint32_t c = uint32_t(J) * uint32_t(nI) + uint32_t(i);
@@ -80,16 +84,30 @@ __global__ __launch_bounds__(64 * kApplyRows) void k_apply(LevelView<T> L,
     const uint32_t e = (i == nI - 1) ? c - uint32_t(nI - 1) : c + 1u;
     const uint32_t sth = (J > 0) ? c - uint32_t(nI) : c;
     const uint32_t nth = (J < nJ - 1) ? c + uint32_t(nI) : c;
-    const size_t t = size_t(k) * P + c;
-    const T* xk = x + size_t(k) * P;
-    const T xc = xk[c];
-    const T xm = x[size_t(k > 0 ? k - 1 : 0) * P + c];
-    const T xp = x[size_t(k + 1 < nz ? k + 1 : k) * P + c];
-    const T h = L.M[t] * xc +
-                hdiff(L.Tlam[k * nJ + J], L.Tth[k * (nJ + 1) + J], L.Tth[k * (nJ + 1) + J + 1],
-                      xc, xk[w], xk[e], xk[sth], xk[nth]) +
-                L.Tr[k * nJ + J] * (xc - xm) + L.Tr[(k + 1) * nJ + J] * (xc - xp);
-    y[t] = HAS_F ? f[t] - h : h;
+    auto clampk = [nz](int k) { return k < 0 ? 0 : (k < nz ? k : nz - 1); };
+    // the column at layers k0-1 .. k0+NL (clamped: a boundary layer is its
+    // own vertical neighbour, and its coupling term vanishes)
+    T xv[NL + 2];
+#pragma unroll
+    for (int d = 0; d < NL + 2; ++d) xv[d] = x[size_t(clampk(k0 - 1 + d)) * P + c];
+    T hs[NL];
+#pragma unroll
+    for (int d = 0; d < NL; ++d) {
+        const int k = clampk(k0 + d);
+        const T* xk = x + size_t(k) * P;
+        const size_t t = size_t(k) * P + c;
+        const T xc = xv[d + 1];
+        const T xm = (k0 + d > 0) ? xv[d] : xc;
+        const T xp = (k0 + d + 1 < nz) ? xv[d + 2] : xc;
+        const T h = L.M[t] * xc +
+                    hdiff(L.Tlam[k * nJ + J], L.Tth[k * (nJ + 1) + J],
+                          L.Tth[k * (nJ + 1) + J + 1], xc, xk[w], xk[e], xk[sth], xk[nth]) +
+                    L.Tr[k * nJ + J] * (xc - xm) + L.Tr[(k + 1) * nJ + J] * (xc - xp);
+        hs[d] = HAS_F ? f[t] - h : h;
+    }
+#pragma unroll
+    for (int d = 0; d < NL; ++d)
+        if (k0 + d < nz) y[size_t(k0 + d) * P + c] = hs[d];
 }
 
 // Refinement step on the finest level, one lane per column (row-tiled
@@ -422,9 +440,8 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ out, T v, long 
 
 template <typename T>
 void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
-    const long long n = L.plane * L.nz;
     const dim3 grid(unsigned((L.nI + 63) / 64), unsigned((L.nJ + kApplyRows - 1) / kApplyRows),
-                    unsigned(L.nz));
+                    unsigned((L.nz + kApplyLayers - 1) / kApplyLayers));
     if (f) k_apply<T, true><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
     else k_apply<T, false><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
 }

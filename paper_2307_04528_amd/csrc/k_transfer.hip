@@ -326,52 +326,104 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(LevelView<T> F, Transfer
         if (k0 + d < nz && g.valid) stb<T>(layer_w(x, k0 + d, Pb), ox, v[d]);
 }
 
-// xc = P^T x, one lane per coarse cell.
+// Layers per lane of the transposed transfers (a lane walks a chunk of
+// layers of its column, the chunk's loads in flight together).
+// (P^T: 4 in FP32, 2 in FP64, whose pairs take twice the registers)
+template <typename T>
+constexpr int prolong_T_layers() {
+    return std::is_same<T, float>::value ? 4 : 2;
+}
+constexpr int kInjectLayers = 8;
+
+// xc = P^T x, one lane per coarse column and chunk of prolong_T_layers layers.
+// A coarse column I gathers fine columns 2I-1 .. 2I+2 of up to four fine
+// rows. Each lane loads its own two (2I, 2I+1) as one pair; the outer two
+// are its neighbour lanes' (shuffled), except at the edges of the
+// wavefront's 64 columns, whose two values are wave-uniform loads. Every
+// lane stays active for the shuffles: lanes past the row's end compute on
+// the last column and store nothing.
 template <typename T>
 __global__ __launch_bounds__(64 * kRowsPerBlock) void k_prolong_T(LevelView<T> F,
                                                                   TransferView<T> X,
                                                                   const T* __restrict__ x,
                                                                   T* __restrict__ xc) {
-    // blocks of 64 coarse columns x kRowsPerBlock coarse rows of one layer
-    const int Ic = int(blockIdx.x) * 64 + int(threadIdx.x);
+    constexpr int NL = prolong_T_layers<T>();
+    using V2 = std::conditional_t<std::is_same<T, float>::value, float2, double2>;
+    // blocks of 64 coarse columns x kRowsPerBlock coarse rows
+    const int lane = int(threadIdx.x);
+    const int Ic0 = int(blockIdx.x) * 64, nIc = X.nIc;
     const int Jc = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
                                                   int(threadIdx.y));
-    const int k = int(blockIdx.z);
-    if (Ic >= X.nIc || Jc >= X.nJc) return;
-    const size_t t = (size_t(k) * X.nJc + size_t(Jc)) * X.nIc + size_t(Ic);
+    const int k0 = int(blockIdx.z) * NL, nz = F.nz;
+    if (Jc >= X.nJc) return;   // wave-uniform
     const int nIf = F.nI;
-    const int iE = 2 * Ic, iO = 2 * Ic + 1;
-    const int iW = (iE == 0) ? nIf - 1 : iE - 1;
-    const int iEE = (iO + 1 == nIf) ? 0 : iO + 1;
+    const bool valid = Ic0 + lane < nIc;
+    const int iE = 2 * (valid ? Ic0 + lane : nIc - 1);
+    // the wavefront's last column, and the fine columns west of its first
+    // and east of its last (wrapping around the circle of longitude)
+    const int lastl = (nIc - Ic0 < 64 ? nIc - Ic0 : 64) - 1;
+    const int iW0 = (Ic0 == 0) ? nIf - 1 : 2 * Ic0 - 1;
+    const int iEE1 = (Ic0 + lastl + 1 == nIc) ? 0 : 2 * (Ic0 + lastl) + 2;
     const T a = T(0.75), b = T(0.25);
-    T acc = 0;
+    size_t roff[4];
+    T wr[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int row = X.ptrow[4 * Jc + e];
-        const T w = X.ptw[4 * Jc + e];
-        const T* r = x + size_t(k) * F.plane + size_t(row < 0 ? 0 : row) * nIf;
-        acc += w * (a * (r[iE] + r[iO]) + b * (r[iW] + r[iEE]));
+        roff[e] = size_t(row < 0 ? 0 : row) * nIf;
+        wr[e] = X.ptw[4 * Jc + e];
     }
-    xc[t] = acc;
+    T acc[NL];
+#pragma unroll
+    for (int d = 0; d < NL; ++d) {
+        const int k = k0 + d < nz ? k0 + d : nz - 1;
+        acc[d] = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const T* r = x + size_t(k) * F.plane + roff[e];
+            const V2 p = *reinterpret_cast<const V2*>(r + iE);
+            const T w0 = r[iW0], e1 = r[iEE1];
+            T rw = __shfl_up(p.y, 1, 64);
+            T ree = __shfl_down(p.x, 1, 64);
+            if (lane == 0) rw = w0;
+            if (lane == lastl) ree = e1;
+            acc[d] += wr[e] * (a * (p.x + p.y) + b * (rw + ree));
+        }
+    }
+    const size_t Pc = size_t(nIc) * X.nJc;
+    const size_t cc = size_t(Jc) * nIc + size_t(Ic0 + lane);
+#pragma unroll
+    for (int d = 0; d < NL; ++d)
+        if (valid && k0 + d < nz) xc[size_t(k0 + d) * Pc + cc] = acc[d];
 }
 
-// x += R^T xc (every child takes its coarse value), one lane per fine cell,
-// in blocks of 64 columns x kRowsPerBlock rows of one layer (the row's
-// coarse row wave-uniform).
+// x += R^T xc (every child takes its coarse value), one lane per fine
+// column and chunk of kInjectLayers layers, in blocks of 64 columns x
+// kRowsPerBlock rows (the row's coarse row wave-uniform).
 template <typename T>
 __global__ __launch_bounds__(64 * kRowsPerBlock) void k_inject_add(LevelView<T> F,
                                                                    TransferView<T> X,
                                                                    const T* __restrict__ xc,
                                                                    T* __restrict__ x) {
-    const int nI = F.nI, nJ = F.nJ, nIc = X.nIc;
+    constexpr int NL = kInjectLayers;
+    const int nI = F.nI, nJ = F.nJ, nIc = X.nIc, nz = F.nz;
     const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
     const int j = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kRowsPerBlock +
                                                  int(threadIdx.y));
-    const int k = int(blockIdx.z);
+    const int k0 = int(blockIdx.z) * NL;
     if (i >= nI || j >= nJ) return;
-    const size_t t = size_t(k) * size_t(F.plane) + size_t(j) * size_t(nI) + size_t(i);
-    const size_t tc = (size_t(k) * X.nJc + size_t(X.crow_of[j])) * size_t(nIc) + size_t(i >> 1);
-    x[t] += xc[tc];
+    const size_t P = size_t(F.plane), Pc = size_t(nIc) * X.nJc;
+    const size_t c = size_t(j) * size_t(nI) + size_t(i);
+    const size_t cc = size_t(X.crow_of[j]) * size_t(nIc) + size_t(i >> 1);
+    T v[NL];
+#pragma unroll
+    for (int d = 0; d < NL; ++d) {
+        const int k = k0 + d < nz ? k0 + d : nz - 1;
+        v[d] = x[size_t(k) * P + c] + xc[size_t(k) * Pc + cc];
+    }
+#pragma unroll
+    for (int d = 0; d < NL; ++d)
+        if (k0 + d < nz) x[size_t(k0 + d) * P + c] = v[d];
 }
 
 }  // namespace
@@ -431,7 +483,8 @@ template <typename T>
 void prolong_transpose(const LevelView<T>& F, const TransferView<T>& X, const T* x, T* xc,
                        hipStream_t s) {
     const dim3 grid(unsigned((X.nIc + 63) / 64),
-                    unsigned((X.nJc + kRowsPerBlock - 1) / kRowsPerBlock), unsigned(F.nz));
+                    unsigned((X.nJc + kRowsPerBlock - 1) / kRowsPerBlock),
+                    unsigned((F.nz + prolong_T_layers<T>() - 1) / prolong_T_layers<T>()));
     k_prolong_T<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, x, xc);
 }
 
@@ -439,7 +492,7 @@ template <typename T>
 void inject_add(const LevelView<T>& F, const TransferView<T>& X, const T* xc, T* x,
                 hipStream_t s) {
     const dim3 grid(unsigned((F.nI + 63) / 64), unsigned((F.nJ + kRowsPerBlock - 1) / kRowsPerBlock),
-                    unsigned(F.nz));
+                    unsigned((F.nz + kInjectLayers - 1) / kInjectLayers));
     k_inject_add<T><<<grid, dim3(64, kRowsPerBlock), 0, s>>>(F, X, xc, x);
 }
 
