@@ -60,10 +60,15 @@ using namespace dev;
 // its column: the chunk's loads are in flight together, and the vertical
 // neighbours come from the layers it already loaded).
 constexpr int kApplyRows = 4;
-constexpr int kApplyLayers = 4;
+// (FP32 2: adjoint solves on 1024x768x70 0.5-0.9 % slower with 4; FP64 4:
+// 0.6 % slower with 2)
+template <typename T>
+constexpr int apply_layers() {
+    return std::is_same<T, float>::value ? 2 : 4;
+}
 
 // y = H x (HAS_F = false) or y = f - H x, one lane per column and chunk of
-// kApplyLayers layers, in blocks of 64 columns x kApplyRows rows (grid:
+// apply_layers layers, in blocks of 64 columns x kApplyRows rows (grid:
 // column groups, row groups, layer chunks): a wavefront takes part of one
 // row, so the row's couplings are wave-uniform and no lane divides its index.
 template <typename T, bool HAS_F>
@@ -71,7 +76,7 @@ __global__ __launch_bounds__(64 * kApplyRows) void k_apply(LevelView<T> L,
                                                            const T* __restrict__ x,
                                                            const T* __restrict__ f,
                                                            T* __restrict__ y) {
-    constexpr int NL = kApplyLayers;
+    constexpr int NL = apply_layers<T>();
     const int nI = L.nI, nJ = L.nJ, nz = L.nz;
     const int i = int(blockIdx.x) * 64 + int(threadIdx.x);
     const int J = __builtin_amdgcn_readfirstlane(int(blockIdx.y) * kApplyRows +
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ out, T v, long 
 template <typename T>
 void apply(const LevelView<T>& L, const T* x, const T* f, T* y, hipStream_t s) {
     const dim3 grid(unsigned((L.nI + 63) / 64), unsigned((L.nJ + kApplyRows - 1) / kApplyRows),
-                    unsigned((L.nz + kApplyLayers - 1) / kApplyLayers));
+                    unsigned((L.nz + apply_layers<T>() - 1) / apply_layers<T>()));
     if (f) k_apply<T, true><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
     else k_apply<T, false><<<grid, dim3(64, kApplyRows), 0, s>>>(L, x, f, y);
 }
